@@ -1,0 +1,229 @@
+"""Seeded synthetic inputs for the HWFV1 workloads.
+
+This module is shared by the CPU oracle and the HIP path.  It holds only the
+recipes that produce inputs (bed, initial state, forcing and the problem
+parameters); none of the method's arithmetic lives here.  All arrays are
+float64, row-major [j, i] with j the row (y, south to north) and i the column
+(x, west to east), sampled at cell centres ((i + 1/2) dx, (j + 1/2) dy).
+
+Workloads (square 2^L x 2^L grids):
+  dambreak_bumps_l6        1 x 1 m box, 8 Gaussian bumps, walls, eps 1e-3,
+                           dam break eta 2 m / 1 m at x = 0.5 m, t_end 0.05 s
+  circular_dambreak_l10    1000 x 1000 m, fractal bed (relief 10 m), 5 m deep
+                           cylinder of radius 100 m over a dry bed, Manning
+                           0.035, open boundaries, 500 steps
+  hydrograph_l12           10 x 10 km, fractal bed (relief 50 m), dry start,
+                           triangular west-edge inflow (500 m^3/s peak at
+                           1800 s, base 3600 s), Manning 0.035, 2000 steps
+  ensemble_64              64 members with L in {8..11}, eps in
+                           {1e-4, 1e-3, 1e-2}, own fractal bed (relief 5-50 m),
+                           dam-break or hydrograph forcing, Manning U(0.01,
+                           0.06), 1000 steps
+  sheetflow_l13            10 x 10 km, fractal bed (relief 500 m), 1 mm sheet,
+                           50 mm/h rain, Manning 0.05, eps 1e-4, 1000 steps
+"""
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+G = 9.80665
+
+
+@dataclass
+class Workload:
+    name: str
+    params: dict
+    h: np.ndarray
+    qx: np.ndarray
+    qy: np.ndarray
+    z: np.ndarray
+    n_steps: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def L(self) -> int:
+        return int(self.params["L"])
+
+
+def base_params(L: int, length: float, eps: float, **kw) -> dict:
+    """Problem parameters with the shared defaults (g, CFL 0.5, h_tol)."""
+    dx = length / (1 << L)
+    p = dict(L=L, eps=eps, g=G, cfl=0.5, h_tol=1e-6, dx=dx, dy=dx,
+             dt_max=0.5 * dx / math.sqrt(G * 1.0), manning_n=0.0,
+             rain_rate=0.0, bc=("wall",) * 4, inlet_y0=0.0, inlet_y1=0.0,
+             q_peak=0.0, t_peak=1.0, t_base=2.0, t_end=math.inf)
+    p.update(kw)
+    return p
+
+
+def cell_centres(L: int, length: float):
+    n = 1 << L
+    dx = length / n
+    c = (np.arange(n) + 0.5) * dx
+    x = np.broadcast_to(c[None, :], (n, n))
+    y = np.broadcast_to(c[:, None], (n, n))
+    return x, y
+
+
+def gaussian_bumps(L: int, length: float, count: int, seed: int,
+                   amp=(0.0, 0.2), width=(0.02, 0.1)) -> np.ndarray:
+    """Sum of Gaussian bumps; amplitude, width (standard deviation) and the
+    two centre coordinates are drawn in that order as arrays of `count`."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(amp[0], amp[1], count)
+    w = rng.uniform(width[0], width[1], count) * length
+    xc = rng.uniform(0.0, 1.0, count) * length
+    yc = rng.uniform(0.0, 1.0, count) * length
+    x, y = cell_centres(L, length)
+    z = np.zeros((1 << L, 1 << L))
+    for k in range(count):
+        r2 = (x - xc[k]) ** 2 + (y - yc[k]) ** 2
+        z += a[k] * np.exp(-r2 / (2.0 * w[k] ** 2))
+    return z
+
+
+def fractal_bed(L: int, relief: float, seed: int,
+                exponent: float = -2.5) -> np.ndarray:
+    """Spectral fractal terrain: white noise shaped so that its power
+    spectrum falls as |k|^exponent, zero mean, scaled to [0, relief]."""
+    n = 1 << L
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal((n, n))
+    spec = np.fft.rfft2(white)
+    del white
+    ky = np.fft.fftfreq(n)[:, None]
+    kx = np.fft.rfftfreq(n)[None, :]
+    k = np.sqrt(kx * kx + ky * ky)
+    k[0, 0] = 1.0
+    spec *= k ** (exponent / 2.0)
+    spec[0, 0] = 0.0
+    del k
+    z = np.fft.irfft2(spec, s=(n, n))
+    del spec
+    lo, hi = z.min(), z.max()
+    z -= lo
+    z *= relief / (hi - lo)
+    return z
+
+
+def dambreak_bumps_l6(seed: int = 1, L: int = 6) -> Workload:
+    length = 1.0
+    p = base_params(L, length, 1e-3, t_end=0.05, bc=("wall",) * 4)
+    z = gaussian_bumps(L, length, 8, seed)
+    x, _ = cell_centres(L, length)
+    eta = np.where(x < 0.5, 2.0, 1.0)
+    h = np.maximum(0.0, eta - z)
+    zero = np.zeros_like(h)
+    return Workload(f"dambreak_bumps_l{L}", p, h, zero, zero.copy(), z,
+                    n_steps=10_000, meta=dict(seed=seed))
+
+
+def circular_dambreak_l10(seed: int = 2, L: int = 10,
+                          n_steps: int = 500) -> Workload:
+    length = 1000.0
+    p = base_params(L, length, 1e-3, manning_n=0.035, bc=("open",) * 4)
+    z = fractal_bed(L, 10.0, seed)
+    x, y = cell_centres(L, length)
+    r = np.sqrt((x - 500.0) ** 2 + (y - 500.0) ** 2)
+    h = np.where(r < 100.0, 5.0, 0.0)
+    zero = np.zeros_like(h)
+    return Workload(f"circular_dambreak_l{L}", p, h, zero, zero.copy(), z,
+                    n_steps=n_steps, meta=dict(seed=seed))
+
+
+def hydrograph_l12(seed: int = 3, L: int = 12, n_steps: int = 2000,
+                   relief: float = 50.0, q_peak: float = 500.0) -> Workload:
+    length = 10_000.0
+    p = base_params(L, length, 1e-3, manning_n=0.035, bc=("open",) * 4,
+                    inlet_y0=4500.0, inlet_y1=5500.0, q_peak=q_peak,
+                    t_peak=1800.0, t_base=3600.0)
+    z = fractal_bed(L, relief, seed)
+    zero = np.zeros((1 << L, 1 << L))
+    return Workload(f"hydrograph_l{L}", p, zero, zero.copy(), zero.copy(), z,
+                    n_steps=n_steps, meta=dict(seed=seed))
+
+
+def sheetflow_l13(seed: int = 5, L: int = 13, n_steps: int = 1000) -> Workload:
+    length = 10_000.0
+    p = base_params(L, length, 1e-4, manning_n=0.05, bc=("open",) * 4,
+                    rain_rate=0.05 / 3600.0)
+    z = fractal_bed(L, 500.0, seed)
+    h = np.full((1 << L, 1 << L), 1e-3)
+    zero = np.zeros_like(h)
+    return Workload(f"sheetflow_l{L}", p, h, zero, zero.copy(), z,
+                    n_steps=n_steps, meta=dict(seed=seed))
+
+
+def ensemble_member(i: int, n_steps: int = 1000, levels=(8, 9, 10, 11),
+                    base_seed: int = 1000) -> Workload:
+    """Member i of the batched ensemble; its own generator draws L, eps,
+    relief, Manning n, the forcing kind and the terrain seed."""
+    rng = np.random.default_rng(base_seed + i)
+    L = int(rng.choice(levels))
+    eps = float(rng.choice([1e-4, 1e-3, 1e-2]))
+    relief = float(rng.uniform(5.0, 50.0))
+    n_m = float(rng.uniform(0.01, 0.06))
+    kind = "dambreak" if rng.uniform() < 0.5 else "hydrograph"
+    tseed = int(rng.integers(0, 2**31 - 1))
+    length = 1000.0
+    z = fractal_bed(L, relief, tseed)
+    zero = np.zeros((1 << L, 1 << L))
+    if kind == "dambreak":
+        p = base_params(L, length, eps, manning_n=n_m, bc=("open",) * 4)
+        x, y = cell_centres(L, length)
+        r = np.sqrt((x - 500.0) ** 2 + (y - 500.0) ** 2)
+        h = np.where(r < 100.0, 5.0, 0.0)
+    else:
+        p = base_params(L, length, eps, manning_n=n_m, bc=("open",) * 4,
+                        inlet_y0=450.0, inlet_y1=550.0, q_peak=50.0,
+                        t_peak=1800.0, t_base=3600.0)
+        h = zero.copy()
+    return Workload(f"ensemble_member_{i}_l{L}", p, h, zero.copy(),
+                    zero.copy(), z, n_steps=n_steps,
+                    meta=dict(member=i, kind=kind, relief=relief,
+                              terrain_seed=tseed))
+
+
+def ensemble_64(n: int = 64, n_steps: int = 1000, levels=(8, 9, 10, 11)):
+    return [ensemble_member(i, n_steps, levels) for i in range(n)]
+
+
+# Small scenarios used by tests ------------------------------------------------
+def lake_at_rest(L: int, eta: float, seed: int, eps: float,
+                 length: float = 1.0, amp=(0.1, 0.6)) -> Workload:
+    """Still water at free-surface eta over Gaussian bumps (dry where the
+    bumps rise above eta), closed walls."""
+    p = base_params(L, length, eps, bc=("wall",) * 4)
+    z = gaussian_bumps(L, length, 6, seed, amp=amp, width=(0.05, 0.15))
+    h = np.maximum(0.0, eta - z)
+    zero = np.zeros_like(h)
+    return Workload(f"lake_at_rest_l{L}", p, h, zero, zero.copy(), z,
+                    n_steps=1000, meta=dict(seed=seed, eta=eta))
+
+
+def dambreak_strip(L: int, h_left: float, h_right: float, x_dam: float,
+                   length: float, eps: float, t_end: float,
+                   axis: str = "x") -> Workload:
+    """1D dam break across a square domain: walls parallel to the flow,
+    open ends, flat frictionless bed."""
+    if axis == "x":
+        bc = ("open", "open", "wall", "wall")
+    else:
+        bc = ("wall", "wall", "open", "open")
+    p = base_params(L, length, eps, bc=bc, t_end=t_end)
+    x, y = cell_centres(L, length)
+    coord = x if axis == "x" else y
+    h = np.where(coord < x_dam, h_left, h_right).astype(np.float64)
+    zero = np.zeros_like(h)
+    return Workload(f"dambreak_strip_l{L}", p, h, zero, zero.copy(),
+                    zero.copy(), n_steps=100_000,
+                    meta=dict(h_left=h_left, h_right=h_right, x_dam=x_dam))
+
+
+BY_NAME = {
+    "dambreak_bumps_l6": dambreak_bumps_l6,
+    "circular_dambreak_l10": circular_dambreak_l10,
+    "hydrograph_l12": hydrograph_l12,
+    "sheetflow_l13": sheetflow_l13,
+}
