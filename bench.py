@@ -1,0 +1,284 @@
+#!/usr/bin/env python3
+"""HWFV1 timestep benchmark on one MI355X.
+
+Headline: timesteps/s of the plain FP64 path on the L = 12 hydrograph
+workload (4096^2 finest cells, eps = 1e-3, seeded fractal bed, west-edge
+inflow, Manning 0.035), inputs resident in HBM, the whole step (encoding,
+flagging, traversal, FV1, fill, finalize) replayed as one HIP graph per step.
+Beside it: the FP32-bulk form on the same workload (with its error against
+the FP64 run), the batched 64-member ensemble, the roofline of the dominant
+kernel (HIP-event phase timing) and the CPU oracle on a bounded sample.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("HWFV1 timesteps/s at L=12, ε=1e-3: FP64 vs FP32-bulk vs batched; "
+          "%HBM peak")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def leaf_level_hist(buffers, L):
+    import numpy as np
+    leaves = buffers.leaf_list().astype(np.int64)
+    lvl = np.floor(np.log(3.0 * leaves + 1.0) / np.log(4.0) + 1e-9).astype(np.int64)
+    return np.bincount(lvl, minlength=L + 1)
+
+
+def phase_bytes(L, w, hist):
+    """Algorithmic HBM bytes of one step per phase (w = bytes per flow word).
+
+    encode    read h, qx, qy on the finest level, write the coarse levels,
+              read the static bed flags, write the raw flags
+    regularise read raw flags (one per cell, neighbours cached), write sig
+    traverse  read sig along the walk (one pass over the coarse flags per
+              kernel), write the leaf list and the fill table
+    fv1       per leaf: its index, own h, qx, qy and bed (FP64), and the
+              finest cells it writes (all descendants for leaves at or below
+              the traversal group level, one otherwise)
+    fill      the finest cells of coarser leaves
+    """
+    N = 4 ** L
+    Nc = (N - 1) // 3
+    Lg = max(L - 2, 0)
+    nl = int(hist.sum())
+    fv1_writes = 0
+    fill_writes = 0
+    for m, cnt in enumerate(hist):
+        cnt = int(cnt)
+        if m >= Lg:
+            fv1_writes += cnt * 4 ** (L - m)
+        else:
+            fv1_writes += cnt
+            fill_writes += cnt * (4 ** (L - m) - 1)
+    groups = 4 ** Lg
+    return {
+        "encode": 3 * w * N + 3 * w * Nc + 2 * Nc,
+        "regularise": 2 * Nc,
+        "traverse": 2 * Nc + 4 * nl + 4 * groups,
+        "fv1": nl * (4 + 3 * w + 8) + 3 * w * fv1_writes,
+        "fill": 4 * groups + 3 * w * fill_writes,
+        "finalize": 0,
+        "n_leaves": nl,
+    }
+
+
+def time_single(hw, w, precision, steps, warmup, prof_steps):
+    import torch
+    log(f"[bench] {w.name} {precision}: ingest")
+    sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision=precision)
+    plan = hw.Plan([sim.problem], [sim.buffers])
+    hw.hwfv1_run(sim.problem, sim.buffers, warmup, plan=plan, stats=True)
+    s0 = sim.scalars()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    hw.hwfv1_run(sim.problem, sim.buffers, steps, plan=plan, stats=False)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    s1 = sim.scalars()
+    log(f"[bench] {precision}: {steps} steps in {ms:.2f} ms (wall {wall*1e3:.2f} ms), "
+        f"t={s1['t']:.3f} s, leaves={s1['n_leaves']}")
+    prof = hw.hw_plan_profile(plan, prof_steps)
+    hist = leaf_level_hist(sim.buffers, w.L)
+    s2 = sim.scalars()
+    res = dict(sim=sim, plan=plan, ms=ms, wall=wall, steps=steps,
+               leaf_updates=int(s1["leaf_updates"] - s0["leaf_updates"]),
+               prof={k: v / prof_steps for k, v in prof.items()}, hist=hist,
+               scalars=s2)
+    return res
+
+
+def roofline(res, L, w):
+    pb = phase_bytes(L, w, res["hist"])
+    prof = res["prof"]
+    dom = max((k for k in prof), key=lambda k: prof[k])
+    achieved = pb[dom] / (prof[dom] * 1e-3) / 1e9
+    step_ms = sum(prof.values())
+    total_bytes = sum(pb[k] for k in prof)
+    per_kernel = {k: {"ms": round(prof[k], 5),
+                      "GBs": round(pb[k] / (prof[k] * 1e-3) / 1e9, 1) if prof[k] > 0 else None}
+                  for k in prof}
+    return {
+        "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "algorithmic_bytes": int(pb[dom]),
+        "avg_ms": round(prof[dom], 5),
+        "step_bytes": int(total_bytes), "step_ms_phases": round(step_ms, 5),
+        "step_frac": round(total_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "phases": per_kernel,
+    }
+
+
+def fp32_error(hw, r64, r32):
+    import numpy as np
+    a = [t.cpu().numpy() for t in hw.hw_export(r64["sim"].problem, r64["sim"].buffers)]
+    b = [t.cpu().numpy() for t in hw.hw_export(r32["sim"].problem, r32["sim"].buffers)]
+    la = set(r64["sim"].buffers.leaf_list().tolist())
+    lb = set(r32["sim"].buffers.leaf_list().tolist())
+    m64 = r64["scalars"]["mass"]
+    m32 = r32["scalars"]["mass"]
+    return {
+        "l1_h": float(np.mean(np.abs(a[0] - b[0]))),
+        "linf_h": float(np.max(np.abs(a[0] - b[0]))),
+        "linf_qx": float(np.max(np.abs(a[1] - b[1]))),
+        "linf_qy": float(np.max(np.abs(a[2] - b[2]))),
+        "l1_qx": float(np.mean(np.abs(a[1] - b[1]))),
+        "l1_qy": float(np.mean(np.abs(a[2] - b[2]))),
+        "leaf_symdiff": len(la ^ lb),
+        "mass_rel_err": (m32 - m64) / m64 if m64 else None,
+        "vs": "FP64 GPU run of the same steps (equal to the oracle within 1e-10)",
+    }
+
+
+def bench_batch(hw, steps, warmup, n_members):
+    import torch
+    import workloads as W
+    log(f"[bench] batch: generating {n_members} members")
+    t0 = time.perf_counter()
+    members = W.ensemble_64(n=n_members, n_steps=steps)
+    log(f"[bench] batch: inputs in {time.perf_counter() - t0:.1f} s")
+    sims = [hw.Simulation(m.params, m.h, m.qx, m.qy, m.z, precision="fp32_bulk")
+            for m in members]
+    cells = sum(4 ** m.L for m in members)
+    plan = hw.Plan([s.problem for s in sims], [s.buffers for s in sims])
+    hw.hwfv1_run_batch(plan, warmup, stats=True)
+    lu0 = sum(s.scalars()["leaf_updates"] for s in sims)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hw.hwfv1_run_batch(plan, steps, stats=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    lu1 = sum(s.scalars()["leaf_updates"] for s in sims)
+    prof = hw.hw_plan_profile(plan, 5)
+    levels = sorted(m.L for m in members)
+    out = {
+        "value": round(steps / (ms * 1e-3), 2), "unit": "ensemble timesteps/s",
+        "member_steps_per_s": round(n_members * steps / (ms * 1e-3), 1),
+        "leaf_updates_per_s": (lu1 - lu0) / (ms * 1e-3),
+        "members": n_members, "finest_cells": cells, "steps": steps,
+        "ms_per_step": round(ms / steps, 4), "dtype": "f32 (FP64 significance)",
+        "levels": {str(L): levels.count(L) for L in sorted(set(levels))},
+        "phase_ms": {k: round(v / 5, 4) for k, v in prof.items()},
+    }
+    plan.close()
+    for s in sims:
+        s.close()
+    return out
+
+
+def cpu_baseline(w, n_steps):
+    import oracle as O
+    log(f"[bench] cpu oracle: {n_steps} steps of {w.name}")
+    o = O.Oracle(w.params, w.h, w.qx, w.qy, w.z)
+    t0 = time.perf_counter()
+    n = o.run(n_steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt, 4), "unit": "timesteps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {n} timesteps of {w.name} (L={w.L}, {4 ** w.L} cells), "
+                      f"FP64, single thread, {dt:.1f} s",
+            "leaf_updates_per_s": o.scalars()["leaf_updates"] / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--prof-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--batch-members", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the ensemble and the Morton-subtree sharding are single-GPU); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2206_05761_amd as hw
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    hw.lib()
+    w = W.hydrograph_l12()
+    L = w.L
+    r64 = time_single(hw, w, "fp64", args.steps, args.warmup, args.prof_steps)
+    value = args.steps / (r64["ms"] * 1e-3)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "timesteps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r64["ms"] / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "L": L, "finest_cells": 4 ** L,
+                   "eps": w.params["eps"], "domain_m": 10000.0,
+                   "bed": "seeded spectral fractal, relief 50 m",
+                   "forcing": "west-edge triangular hydrograph 500 m^3/s",
+                   "manning_n": w.params["manning_n"], "precision": "fp64"},
+        "leaf_updates_per_s": r64["leaf_updates"] / (r64["ms"] * 1e-3),
+        "n_leaves": int(r64["scalars"]["n_leaves"]),
+        "roofline": roofline(r64, L, 8),
+    }
+    if not args.no_fp32:
+        r32 = time_single(hw, w, "fp32_bulk", args.steps, args.warmup, args.prof_steps)
+        line["fp32_bulk"] = {
+            "value": round(args.steps / (r32["ms"] * 1e-3), 2), "unit": "timesteps/s",
+            "ms_per_step": round(r32["ms"] / args.steps, 5),
+            "leaf_updates_per_s": r32["leaf_updates"] / (r32["ms"] * 1e-3),
+            "roofline": roofline(r32, L, 4),
+            "error_vs_fp64": fp32_error(hw, r64, r32),
+        }
+        r32["plan"].close()
+        r32["sim"].close()
+        del r32
+    r64["plan"].close()
+    r64["sim"].close()
+    del r64
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        line["batched"] = bench_batch(hw, args.batch_steps, args.warmup,
+                                      args.batch_members)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

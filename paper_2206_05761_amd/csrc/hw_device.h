@@ -1,0 +1,160 @@
+// Device-side definitions shared by the HWFV1 kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hwfv1.h"
+
+namespace hw {
+
+constexpr int kBlock = 256;             // workgroup size of most kernels
+constexpr int kWave = 64;               // CDNA wavefront
+constexpr uint32_t kNone = 0xffffffffu; // "no coarse leaf" marker
+constexpr int kPartial = 8;             // doubles per FV1 partial record
+constexpr int kMaxScen = 64;            // problems per batch
+constexpr int kMaxFv1Grid = 8192;
+
+// Everything a kernel needs to know about one problem.  Lives in device
+// memory (the workspace for single-problem calls, the plan for batches).
+struct Desc {
+    int32_t L, precision, bc[4];
+    int32_t group_level;   // level of the traversal groups (max(L-2, 0))
+    int32_t pad0;
+    double eps, g, cfl, h_tol, dx, dy, dt_max, manning_n, rain_rate;
+    double inlet_y0, inlet_y1, q_peak, t_peak, t_base, t_end;
+    void* fine[2][3];
+    void* coarse[3];
+    double* zhier;
+    uint8_t* zsig;
+    uint8_t* raw;
+    uint8_t* sig;
+    uint32_t* leaves;
+    hw_scalars* scal;
+    uint32_t* tcount;      // traversal workgroup counts / offsets
+    uint32_t* big_src;     // per group: leaf index of a coarser leaf or kNone
+    double* partials;      // FV1 / ingest partial records, kPartial each
+    uint32_t ntrav;        // traversal workgroups of this problem
+    uint32_t pad1;
+};
+
+// Work decomposition of one launch: problem s owns workgroups
+// [prefix[s], prefix[s+1]).  prefix == nullptr means one problem that owns
+// every workgroup.
+struct Launch {
+    const Desc* descs;
+    const uint32_t* prefix;
+    int32_t n;
+};
+
+__host__ __device__ inline uint64_t level_off(int n)
+{
+    return ((uint64_t(1) << (2 * n)) - 1) / 3;
+}
+
+__host__ __device__ inline uint32_t part1by1(uint32_t x)
+{
+    x &= 0x0000ffffu;
+    x = (x | (x << 8)) & 0x00ff00ffu;
+    x = (x | (x << 4)) & 0x0f0f0f0fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+__host__ __device__ inline uint32_t compact1by1(uint32_t x)
+{
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0f0f0f0fu;
+    x = (x | (x >> 4)) & 0x00ff00ffu;
+    x = (x | (x >> 8)) & 0x0000ffffu;
+    return x;
+}
+
+__host__ __device__ inline uint32_t morton(uint32_t i, uint32_t j)
+{
+    return part1by1(i) | (part1by1(j) << 1);
+}
+
+// Level of a hierarchy Z-order index: the n with (4^n-1)/3 <= idx <
+// (4^(n+1)-1)/3, i.e. floor(log4(3 idx + 1)).
+__device__ inline int level_of(uint32_t idx)
+{
+    return (31 - __clz(3u * idx + 1u)) >> 1;
+}
+
+// Problem of workgroup b and the workgroup's index inside that problem.
+__device__ inline int scen_of(const Launch& l, uint32_t b, uint32_t& local)
+{
+    if (!l.prefix) {
+        local = b;
+        return 0;
+    }
+    int lo = 0, hi = l.n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (l.prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    local = b - l.prefix[lo];
+    return lo;
+}
+
+// ---- reductions ---------------------------------------------------------
+template <typename V>
+__device__ inline V wave_sum(V v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename V>
+__device__ inline V wave_max(V v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        V w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// Inclusive prefix sum over a wave.
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t w = __shfl_up(v, o);
+        if (lane >= o) v += w;
+    }
+    return v;
+}
+
+// Exclusive prefix over a workgroup of blockDim.x threads (multiple of 64,
+// at most 1024); returns the exclusive prefix and the workgroup total.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* lds,
+                                           uint32_t& total)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) lds[wid] = inc;
+    __syncthreads();
+    if (wid == 0) {
+        uint32_t w = lane < nw ? lds[lane] : 0u;
+        uint32_t wi = wave_incl_scan(w);
+        if (lane < nw) lds[lane] = wi - w;
+        if (lane == nw - 1) lds[16] = wi;
+    }
+    __syncthreads();
+    uint32_t excl = inc - v + lds[wid];
+    total = lds[16];
+    __syncthreads();
+    return excl;
+}
+
+}  // namespace hw

@@ -1,0 +1,1067 @@
+// HWFV1 timestep kernels for gfx950 (CDNA4, wave64).
+//
+// Phases of one timestep (Algorithm 3):
+//   k_encode      Haar encoding (Eq. 3a-3d, Algorithm 1) of h, qx, qy over a
+//                 Morton tile, several levels per pass, fused with the FP64
+//                 significance test; the bed uses the same kernel at ingest.
+//   k_regularise  refine the face neighbours of significant cells.
+//   k_traverse    per-group walk down the significance tree (Algorithm 5) and
+//                 ordered compaction of the leaves (count, scan, emit).
+//   k_fv1         FV1 update of every leaf with same-level neighbours (Fig. 3),
+//                 write-back to the finest descendants, partial reductions.
+//   k_fill        copy-down of leaves coarser than a traversal group.
+//   k_finalize    t += dt, CFL timestep, s_max, mass (minimum reduction of
+//                 Section 2.2.3), flip of the finest buffer set.
+//
+// Floating-point expressions are written in the same order as the method's
+// definition so that, compiled without contraction, the FP64 path performs
+// the same IEEE operations in the same order for every cell value.
+#include "hw_device.h"
+
+#include <math.h>
+
+namespace hw {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__global__ void k_set_desc(Desc d, Desc* dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = d;
+}
+
+struct Haar {
+    double s, da, db, dg;
+};
+
+// Eq. 3a-3d with orthonormal Haar taps and the averaging factor 1/2: every
+// tap product is +-1/2, so each coefficient is a quarter of a sum or a
+// difference of the column pairs (s0 + s2), (s1 + s3), (s0 - s2), (s1 - s3).
+__device__ inline Haar haar(double c0, double c1, double c2, double c3)
+{
+    double a = c0 + c2;
+    double b = c1 + c3;
+    double ad = c0 - c2;
+    double bd = c1 - c3;
+    Haar h;
+    h.s = 0.25 * (a + b);
+    h.da = 0.25 * (ad + bd);
+    h.db = 0.25 * (a - b);
+    h.dg = 0.25 * (ad - bd);
+    return h;
+}
+
+// Algorithm 1 significance test, in FP64: max |detail| / s_max >= 2^(n-L) eps.
+__device__ inline bool significant(const Haar& h, double smax, double thr)
+{
+    double a = fabs(h.da);
+    double b = fabs(h.db);
+    double g = fabs(h.dg);
+    double m = a > b ? a : b;
+    m = m > g ? m : g;
+    return (m / smax) >= thr;
+}
+
+__device__ inline void load4(const double* p, double o[4])
+{
+    double2 a = *reinterpret_cast<const double2*>(p);
+    double2 b = *reinterpret_cast<const double2*>(p + 2);
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+}
+
+__device__ inline void load4(const float* p, double o[4])
+{
+    float4 a = *reinterpret_cast<const float4*>(p);
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = a.z;
+    o[3] = a.w;
+}
+
+// ---------------------------------------------------------------------------
+// Encoding with fused significance flags
+// ---------------------------------------------------------------------------
+//
+// A pass covers `tl` levels: the workgroup owns a tile of 4^lv cells of the
+// input level n_in (lv = min(tl, n_in)) and produces levels n_in-1 .. n_in-lv.
+// Each thread first reduces 4^cp consecutive input cells in registers (cp = 1
+// or 2 levels), the remaining levels go through LDS.  Pass 0 reads the
+// finest level; pass k reads the coarse level written by pass k-1.
+//
+// FLOW: h, qx, qy of the current step (flags OR-ed with the static bed
+// flags into raw); otherwise the bed (flags into zsig).
+
+template <typename T, int NV, bool FLOW, bool DET>
+__global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
+                                                   int tl, int cpt,
+                                                   double* details)
+{
+    uint32_t b;
+    const int s = scen_of(lc, blockIdx.x, b);
+    const Desc& d = lc.descs[s];
+    const hw_scalars* sc = d.scal;
+    if (FLOW && sc->done) return;
+    const int L = d.L;
+    const int n_in = L - pass * tl;
+    if (n_in <= 0) return;
+    const int lv = n_in < tl ? n_in : tl;
+    const int n_lo = n_in - lv;
+    const int cp = cpt < lv ? cpt : lv;
+    const int tid = threadIdx.x;
+    const uint64_t ncoarse = level_off(L);
+
+    const T* src[NV];
+    double smax[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (FLOW) {
+            src[v] = pass == 0
+                         ? reinterpret_cast<const T*>(d.fine[sc->cur][v])
+                         : reinterpret_cast<const T*>(d.coarse[v]) +
+                               level_off(n_in);
+            smax[v] = sc->smax[v];
+        } else {
+            src[v] = reinterpret_cast<const T*>(d.zhier + level_off(n_in));
+            smax[v] = sc->smax[3];
+        }
+    }
+    uint8_t* flags = FLOW ? d.raw : d.zsig;
+
+    auto dst_of = [&](int v, int n) -> T* {
+        if (FLOW) return reinterpret_cast<T*>(d.coarse[v]) + level_off(n);
+        return reinterpret_cast<T*>(d.zhier + level_off(n));
+    };
+
+    // Encode one cell (n, k) from its four children, store it, flag it.
+    auto emit = [&](int n, uint64_t k, const double (*ch)[4], double* out) {
+        const double thr = ldexp(d.eps, n - L);
+        bool f = false;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            Haar hh = haar(ch[v][0], ch[v][1], ch[v][2], ch[v][3]);
+            T sv = (T)hh.s;
+            dst_of(v, n)[k] = sv;
+            out[v] = (double)sv;
+            if (significant(hh, smax[v], thr)) f = true;
+            if (DET) {
+                const uint64_t o = level_off(n) + k;
+                details[(uint64_t)(v * 3 + 0) * ncoarse + o] = hh.da;
+                details[(uint64_t)(v * 3 + 1) * ncoarse + o] = hh.db;
+                details[(uint64_t)(v * 3 + 2) * ncoarse + o] = hh.dg;
+            }
+        }
+        const uint64_t o = level_off(n) + k;
+        uint8_t fl = f ? 1 : 0;
+        if (FLOW) fl |= d.zsig[o];
+        flags[o] = fl ? 1 : 0;
+    };
+
+    const int n_mid = n_in - cp;                  // level held per thread
+    const uint32_t M = 1u << (2 * (lv - cp));     // active threads
+    double p[NV];
+    if ((uint32_t)tid < M) {
+        const uint64_t tile_in = (uint64_t)b << (2 * lv);
+        if (cp == 1) {
+            const uint64_t base = tile_in + 4ull * tid;
+            double ch[NV][4];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                if (FLOW && pass == 0) load4(src[v] + base, ch[v]);
+                else
+                    for (int q = 0; q < 4; ++q) ch[v][q] = (double)src[v][base + q];
+            }
+            emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + tid, ch, p);
+        } else {
+            const uint64_t base = tile_in + 16ull * tid;
+            double mid[NV][4];
+            for (int qq = 0; qq < 4; ++qq) {
+                double ch[NV][4];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    if (FLOW && pass == 0) load4(src[v] + base + 4 * qq, ch[v]);
+                    else
+                        for (int q = 0; q < 4; ++q)
+                            ch[v][q] = (double)src[v][base + 4 * qq + q];
+                }
+                double o[NV];
+                emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + 4ull * tid + qq,
+                     ch, o);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) mid[v][qq] = o[v];
+            }
+            emit(n_in - 2, ((uint64_t)b << (2 * (lv - 2))) + tid, mid, p);
+        }
+    }
+
+    // Remaining levels of the tile through LDS.
+    __shared__ double lds[2][NV][kBlock];
+    if ((uint32_t)tid < M) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) lds[0][v][tid] = p[v];
+    }
+    __syncthreads();
+    int pp = 0;
+    uint32_t cnt = M;
+    for (int n = n_mid - 1; n >= n_lo; --n) {
+        cnt >>= 2;
+        if ((uint32_t)tid < cnt) {
+            double ch[NV][4];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                for (int q = 0; q < 4; ++q) ch[v][q] = lds[pp][v][4 * tid + q];
+            double o[NV];
+            emit(n, (uint64_t)b * cnt + tid, ch, o);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) lds[pp ^ 1][v][tid] = o[v];
+        }
+        __syncthreads();
+        pp ^= 1;
+    }
+}
+
+// Significance test alone (for the standalone flag entry point): details of
+// every coarse cell recomputed from its stored children.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_flag_only(Launch lc)
+{
+    uint32_t b;
+    const int s = scen_of(lc, blockIdx.x, b);
+    const Desc& d = lc.descs[s];
+    const hw_scalars* sc = d.scal;
+    if (sc->done) return;
+    const int L = d.L;
+    const uint64_t c = (uint64_t)b * kBlock + threadIdx.x;
+    if (c >= level_off(L)) return;
+    const int n = level_of((uint32_t)c);
+    const uint64_t k = c - level_off(n);
+    const double thr = ldexp(d.eps, n - L);
+    bool f = false;
+    for (int v = 0; v < 3; ++v) {
+        const T* ch = n + 1 == L
+                          ? reinterpret_cast<const T*>(d.fine[sc->cur][v])
+                          : reinterpret_cast<const T*>(d.coarse[v]) +
+                                level_off(n + 1);
+        Haar hh = haar((double)ch[4 * k], (double)ch[4 * k + 1],
+                       (double)ch[4 * k + 2], (double)ch[4 * k + 3]);
+        if (significant(hh, sc->smax[v], thr)) f = true;
+    }
+    uint8_t fl = (f ? 1 : 0) | d.zsig[c];
+    d.raw[c] = fl ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Regularisation: sig = raw of the cell or of any in-domain face neighbour
+// on the same level.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_regularise(Launch lc)
+{
+    uint32_t b;
+    const int s = scen_of(lc, blockIdx.x, b);
+    const Desc& d = lc.descs[s];
+    if (d.scal->done) return;
+    const uint64_t c = (uint64_t)b * kBlock + threadIdx.x;
+    if (c >= level_off(d.L)) return;
+    const int n = level_of((uint32_t)c);
+    const uint32_t k = (uint32_t)(c - level_off(n));
+    const uint32_t i = compact1by1(k), j = compact1by1(k >> 1);
+    const uint32_t S = 1u << n;
+    const uint8_t* raw = d.raw + level_off(n);
+    uint8_t f = raw[k];
+    if (i > 0) f |= raw[morton(i - 1, j)];
+    if (i + 1 < S) f |= raw[morton(i + 1, j)];
+    if (j > 0) f |= raw[morton(i, j - 1)];
+    if (j + 1 < S) f |= raw[morton(i, j + 1)];
+    d.sig[c] = f ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Traversal and ordered compaction
+// ---------------------------------------------------------------------------
+//
+// A thread owns one group cell g on level Lg = max(L-2, 0), i.e. the 4^(L-Lg)
+// finest cells below it.  It walks from the root towards g (Algorithm 5);
+// if it stops above Lg at a coarser leaf it emits that leaf only when g holds
+// the leaf's first finest descendant (so each leaf is listed once), and
+// records the leaf for the copy-down; otherwise it expands the at most two
+// levels below g.  Leaves come out in ascending first-descendant order.
+
+template <bool WRITE>
+__device__ inline int walk_group(const Desc& d, uint32_t g, uint32_t* out,
+                                 uint32_t& big)
+{
+    const int L = d.L;
+    const int Lg = d.group_level;
+    const uint8_t* sig = d.sig;
+    int cnt = 0;
+    big = kNone;
+    int n = 0;
+    for (; n < Lg; ++n) {
+        const uint32_t k = g >> (2 * (Lg - n));
+        if (!sig[level_off(n) + k]) break;
+    }
+    if (n < Lg) {
+        const uint32_t k = g >> (2 * (Lg - n));
+        const uint32_t idx = (uint32_t)level_off(n) + k;
+        big = idx;
+        if ((g & ((1u << (2 * (Lg - n))) - 1u)) == 0) {
+            if (WRITE) out[cnt] = idx;
+            ++cnt;
+        }
+        return cnt;
+    }
+    if (!sig[level_off(Lg) + g]) {
+        if (WRITE) out[cnt] = (uint32_t)level_off(Lg) + g;
+        return cnt + 1;
+    }
+    const int n1 = Lg + 1;
+    for (uint32_t c1 = 0; c1 < 4; ++c1) {
+        const uint32_t k1 = 4 * g + c1;
+        if (n1 == L || !sig[level_off(n1) + k1]) {
+            if (WRITE) out[cnt] = (uint32_t)level_off(n1) + k1;
+            ++cnt;
+        } else {
+            for (uint32_t c2 = 0; c2 < 4; ++c2) {
+                if (WRITE) out[cnt] = (uint32_t)level_off(n1 + 1) + 4 * k1 + c2;
+                ++cnt;
+            }
+        }
+    }
+    return cnt;
+}
+
+template <bool EMIT>
+__global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
+{
+    __shared__ uint32_t lds[32];
+    uint32_t lb;
+    const int s = scen_of(lc, blockIdx.x, lb);
+    const Desc& d = lc.descs[s];
+    if (d.scal->done) return;
+    const uint32_t ngroups = 1u << (2 * d.group_level);
+    const uint32_t g = lb * kBlock + threadIdx.x;
+    const bool active = g < ngroups;
+    uint32_t big = kNone;
+    const uint32_t cnt = active ? (uint32_t)walk_group<false>(d, g, nullptr, big) : 0u;
+    uint32_t total;
+    const uint32_t excl = block_excl_scan(cnt, lds, total);
+    if (!EMIT) {
+        if (threadIdx.x == 0) d.tcount[lb] = total;
+        return;
+    }
+    if (active) {
+        const uint32_t base = d.tcount[lb] + excl;
+        walk_group<true>(d, g, d.leaves + base, big);
+        d.big_src[g] = big;
+    }
+}
+
+// Exclusive scan of the per-workgroup leaf counts of one problem (one
+// workgroup per problem); the total is the leaf count of the step.
+__global__ __launch_bounds__(1024) void k_trav_scan(const Desc* descs)
+{
+    __shared__ uint32_t lds[32];
+    const Desc& d = descs[blockIdx.x];
+    if (d.scal->done) return;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < d.ntrav; base += blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t v = i < d.ntrav ? d.tcount[i] : 0u;
+        uint32_t total;
+        const uint32_t excl = block_excl_scan(v, lds, total);
+        if (i < d.ntrav) d.tcount[i] = carry + excl;
+        carry += total;
+    }
+    if (threadIdx.x == 0) d.scal->n_leaves = carry;
+}
+
+// ---------------------------------------------------------------------------
+// FV1 update on the leaves
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct Cell {
+    T h, qx, qy;
+    double z;
+};
+
+template <typename T>
+__device__ inline Cell<T> load_cell(const Desc& d, int cur, int n, uint32_t k)
+{
+    Cell<T> c;
+    if (n == d.L) {
+        c.h = reinterpret_cast<const T*>(d.fine[cur][0])[k];
+        c.qx = reinterpret_cast<const T*>(d.fine[cur][1])[k];
+        c.qy = reinterpret_cast<const T*>(d.fine[cur][2])[k];
+    } else {
+        const uint64_t o = level_off(n) + k;
+        c.h = reinterpret_cast<const T*>(d.coarse[0])[o];
+        c.qx = reinterpret_cast<const T*>(d.coarse[1])[o];
+        c.qy = reinterpret_cast<const T*>(d.coarse[2])[o];
+    }
+    c.z = d.zhier[level_off(n) + k];
+    return c;
+}
+
+// Neighbour of leaf (m, c) in direction dir (Fig. 3): the level-m cell on
+// that side if all its ancestors are significant, else the coarser leaf on
+// its path; a ghost copy of the leaf outside the domain.  Ancestors shared
+// with the leaf itself are significant, so the walk starts at the first
+// level where the two paths differ.
+template <typename T>
+__device__ inline Cell<T> neighbour(const Desc& d, int cur, int m, uint32_t c,
+                                    uint32_t i, uint32_t j, int dir,
+                                    const Cell<T>& own)
+{
+    const uint32_t S = 1u << m;
+    uint32_t ii = i, jj = j;
+    bool out = false;
+    if (dir == HW_W) { out = i == 0; ii = i - 1; }
+    if (dir == HW_E) { out = i + 1 >= S; ii = i + 1; }
+    if (dir == HW_S) { out = j == 0; jj = j - 1; }
+    if (dir == HW_N) { out = j + 1 >= S; jj = j + 1; }
+    if (out) {
+        Cell<T> g = own;
+        if (d.bc[dir] == HW_BC_WALL) {
+            if (dir == HW_W || dir == HW_E) g.qx = -g.qx;
+            else g.qy = -g.qy;
+        }
+        return g;
+    }
+    const uint32_t cd = morton(ii, jj);
+    const uint32_t x = c ^ cd;
+    const int p = (31 - __clz(x)) >> 1;   // highest differing bit pair
+    for (int n = m - p; n < m; ++n) {
+        const uint32_t k = cd >> (2 * (m - n));
+        if (!d.sig[level_off(n) + k]) return load_cell<T>(d, cur, n, k);
+    }
+    return load_cell<T>(d, cur, m, cd);
+}
+
+template <typename T>
+__device__ inline T velocity(T h, T q, T tol)
+{
+    return h > tol ? q / h : T(0);
+}
+
+// One face between a left and a right state (normal velocity un, tangential
+// ut): hydrostatic reconstruction of the depths against the face bed
+// max(z_l, z_r), written with bed differences, then the HLL flux with
+// two-rarefaction wave-speed estimates and dry-side speeds u -/+ 2c.
+template <typename T>
+__device__ inline void face_flux(T hl, T unl, T utl, double zl, T hr, T unr,
+                                 T utr, double zr, T g, T tol, T F[3],
+                                 T& hls_out, T& hrs_out)
+{
+    const T dzl = (T)(zr - zl);
+    const T dzr = (T)(zl - zr);
+    T hls = hl - (dzl > T(0) ? dzl : T(0));
+    T hrs = hr - (dzr > T(0) ? dzr : T(0));
+    if (!(hls > T(0))) hls = T(0);
+    if (!(hrs > T(0))) hrs = T(0);
+    hls_out = hls;
+    hrs_out = hrs;
+    if (hls <= tol && hrs <= tol) {
+        F[0] = T(0);
+        F[1] = T(0);
+        F[2] = T(0);
+        return;
+    }
+    const T cl = sqrt(g * hls);
+    const T cr = sqrt(g * hrs);
+    const T ustar = T(0.5) * (unl + unr) + cl - cr;
+    const T cstar = T(0.5) * (cl + cr) + T(0.25) * (unl - unr);
+    T sl, sr;
+    if (hls <= tol) {
+        sl = unr - T(2) * cr;
+    } else {
+        const T a = unl - cl;
+        const T b = ustar - cstar;
+        sl = a < b ? a : b;
+    }
+    if (hrs <= tol) {
+        sr = unl + T(2) * cl;
+    } else {
+        const T a = unr + cr;
+        const T b = ustar + cstar;
+        sr = a > b ? a : b;
+    }
+    const T ql = hls * unl;
+    const T qr = hrs * unr;
+    const T Ul[3] = {hls, ql, hls * utl};
+    const T Ur[3] = {hrs, qr, hrs * utr};
+    const T Fl[3] = {ql, ql * unl + T(0.5) * g * hls * hls, ql * utl};
+    const T Fr[3] = {qr, qr * unr + T(0.5) * g * hrs * hrs, qr * utr};
+    if (sl >= T(0)) {
+        F[0] = Fl[0];
+        F[1] = Fl[1];
+        F[2] = Fl[2];
+    } else if (sr <= T(0)) {
+        F[0] = Fr[0];
+        F[1] = Fr[1];
+        F[2] = Fr[2];
+    } else {
+        const T slsr = sl * sr;
+        const T den = sr - sl;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            F[k] = ((sr * Fl[k] - sl * Fr[k]) + slsr * (Ur[k] - Ul[k])) / den;
+    }
+}
+
+__device__ inline double inflow_rate(const Desc& d, double t)
+{
+    if (!(d.q_peak > 0.0)) return 0.0;
+    if (t <= d.t_peak) return d.q_peak * t / d.t_peak;
+    if (t <= d.t_base) return d.q_peak * (d.t_base - t) / (d.t_base - d.t_peak);
+    return 0.0;
+}
+
+template <typename T>
+__device__ inline double wave_speed(T h, T qx, T qy, T g, T tol)
+{
+    if (!(h > tol)) return 0.0;
+    const T c = sqrt(g * h);
+    const T u = qx / h;
+    const T v = qy / h;
+    const T su = fabs(u) + c;
+    const T sv = fabs(v) + c;
+    return (double)(su > sv ? su : sv);
+}
+
+// Per-thread accumulators; the same 8 slots form one partial record:
+// [0] wave speed, [1] |h|, [2] |qx|, [3] |qy| (maxima), [4] mass, [5] clips
+// (sums), [6] non-finite flag, [7] |z| (maxima; |z| only during ingest).
+struct Acc {
+    double v[kPartial];
+};
+
+__device__ inline bool slot_is_sum(int q) { return q == 4 || q == 5; }
+
+__device__ inline void acc_reset(Acc& a)
+{
+#pragma unroll
+    for (int q = 0; q < kPartial; ++q) a.v[q] = 0.0;
+}
+
+__device__ inline void acc_max(Acc& a, int q, double x)
+{
+    a.v[q] = x > a.v[q] ? x : a.v[q];
+}
+
+// Combine a record into the accumulators (max or sum per slot).
+__device__ inline void acc_add_record(Acc& a, const double* r)
+{
+#pragma unroll
+    for (int q = 0; q < kPartial; ++q) {
+        if (slot_is_sum(q)) a.v[q] += r[q];
+        else acc_max(a, q, r[q]);
+    }
+}
+
+// Reduce the per-thread accumulators of the workgroup into rec (rec is
+// combined, not overwritten).  Must be reached by the whole workgroup.
+__device__ inline void acc_flush(Acc& a, double (*red)[kPartial], double* rec)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < kPartial; ++q) {
+        const double x = slot_is_sum(q) ? wave_sum(a.v[q]) : wave_max(a.v[q]);
+        if (lane == 0) red[wid][q] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x / kWave;
+        for (int q = 0; q < kPartial; ++q) {
+            double r = red[0][q];
+            for (int w = 1; w < nw; ++w) {
+                if (slot_is_sum(q)) r += red[w][q];
+                else r = red[w][q] > r ? red[w][q] : r;
+            }
+            if (slot_is_sum(q)) rec[q] += r;
+            else rec[q] = r > rec[q] ? r : rec[q];
+        }
+    }
+    __syncthreads();
+    acc_reset(a);
+}
+
+template <typename T>
+__device__ inline void fv1_leaf(const Desc& d, int cur, double t, double dt,
+                                uint32_t idx, Acc& acc)
+{
+    const int L = d.L;
+    const int m = level_of(idx);
+    const uint32_t c = idx - (uint32_t)level_off(m);
+    const uint32_t i = compact1by1(c), j = compact1by1(c >> 1);
+    const T g = (T)d.g;
+    const T tol = (T)d.h_tol;
+    const double dxm = ldexp(d.dx, L - m);
+    const double dym = ldexp(d.dy, L - m);
+
+    const Cell<T> own = load_cell<T>(d, cur, m, c);
+    const Cell<T> w = neighbour<T>(d, cur, m, c, i, j, HW_W, own);
+    const Cell<T> e = neighbour<T>(d, cur, m, c, i, j, HW_E, own);
+    const Cell<T> so = neighbour<T>(d, cur, m, c, i, j, HW_S, own);
+    const Cell<T> no = neighbour<T>(d, cur, m, c, i, j, HW_N, own);
+
+    const T uc = velocity(own.h, own.qx, tol), vc = velocity(own.h, own.qy, tol);
+    const T uw = velocity(w.h, w.qx, tol), vw = velocity(w.h, w.qy, tol);
+    const T ue = velocity(e.h, e.qx, tol), ve = velocity(e.h, e.qy, tol);
+    const T us = velocity(so.h, so.qx, tol), vs = velocity(so.h, so.qy, tol);
+    const T un = velocity(no.h, no.qx, tol), vn = velocity(no.h, no.qy, tol);
+
+    T FE[3], FW[3], GN[3], GS[3];
+    T hcE, hcW, hcN, hcS, unused;
+    face_flux<T>(own.h, uc, vc, own.z, e.h, ue, ve, e.z, g, tol, FE, hcE, unused);
+    face_flux<T>(w.h, uw, vw, w.z, own.h, uc, vc, own.z, g, tol, FW, unused, hcW);
+    face_flux<T>(own.h, vc, uc, own.z, no.h, vn, un, no.z, g, tol, GN, hcN, unused);
+    face_flux<T>(so.h, vs, us, so.z, own.h, vc, uc, own.z, g, tol, GS, unused, hcS);
+
+    // Audusse bed-slope term: own-depth pressure minus reconstructed-depth
+    // pressure on each face, added to the normal momentum flux.
+    const T hg = T(0.5) * g;
+    const T h2 = own.h * own.h;
+    const T PE = hg * (h2 - hcE * hcE);
+    const T PW = hg * (h2 - hcW * hcW);
+    const T PN = hg * (h2 - hcN * hcN);
+    const T PS = hg * (h2 - hcS * hcS);
+    const T rx = (T)(dt / dxm);
+    const T ry = (T)(dt / dym);
+    T h = own.h - rx * (FE[0] - FW[0]) - ry * (GN[0] - GS[0]);
+    T qx = own.qx - rx * ((FE[1] + PE) - (FW[1] + PW)) - ry * (GN[2] - GS[2]);
+    T qy = own.qy - rx * (FE[2] - FW[2]) - ry * ((GN[1] + PN) - (GS[1] + PS));
+
+    // sources: rain, west-edge inflow, positivity, dry cells, friction
+    if (d.rain_rate != 0.0) h = h + (T)(dt * d.rain_rate);
+    if (i == 0 && d.q_peak > 0.0) {
+        const double y_lo = (double)j * dym;
+        const double lo = y_lo > d.inlet_y0 ? y_lo : d.inlet_y0;
+        const double yhi = y_lo + dym;
+        const double hi = yhi < d.inlet_y1 ? yhi : d.inlet_y1;
+        const double overlap = hi - lo;
+        if (overlap > 0.0) {
+            const double width = d.inlet_y1 - d.inlet_y0;
+            const double q = inflow_rate(d, t);
+            h = h + (T)(dt * q * overlap / (width * dxm * dym));
+        }
+    }
+    if (h < T(0)) {
+        h = T(0);
+        acc.v[5] += 1.0;
+    }
+    if (h <= tol) {
+        qx = T(0);
+        qy = T(0);
+    } else if (d.manning_n > 0.0) {
+        const T nm = (T)d.manning_n;
+        const T speed = sqrt(qx * qx + qy * qy) / h;
+        const T cf = g * nm * nm / cbrt(h);
+        const T den = T(1) + (T)dt * cf * speed / h;
+        qx = qx / den;
+        qy = qy / den;
+    }
+
+    // write-back: every finest descendant of the leaf in the other set,
+    // except for leaves coarser than a traversal group (k_fill copies
+    // those from the first descendant)
+    const int sh = 2 * (L - m);
+    const uint64_t f0 = (uint64_t)c << sh;
+    T* dh = reinterpret_cast<T*>(d.fine[cur ^ 1][0]);
+    T* dqx = reinterpret_cast<T*>(d.fine[cur ^ 1][1]);
+    T* dqy = reinterpret_cast<T*>(d.fine[cur ^ 1][2]);
+    const uint32_t cnt = m >= d.group_level ? (1u << sh) : 1u;
+    for (uint32_t q = 0; q < cnt; ++q) {
+        dh[f0 + q] = h;
+        dqx[f0 + q] = qx;
+        dqy[f0 + q] = qy;
+    }
+
+    acc_max(acc, 0, wave_speed<T>(h, qx, qy, g, tol));
+    acc_max(acc, 1, fabs((double)h));
+    acc_max(acc, 2, fabs((double)qx));
+    acc_max(acc, 3, fabs((double)qy));
+    acc.v[4] += ((double)h * dxm) * dym;
+    if (!(isfinite((double)h) && isfinite((double)qx) && isfinite((double)qy)))
+        acc.v[6] = 1.0;
+}
+
+// Persistent FV1 kernel over the leaves of n problems.  The leaves of every
+// problem are cut into chunks of kBlock; the chunk sequence of all problems
+// is split into 8 contiguous segments, one per XCD (workgroups are dispatched
+// to XCDs round-robin), so that neighbouring leaves share an L2.  Each
+// workgroup leaves one partial record per problem.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fv1(const Desc* descs, int n)
+{
+    __shared__ uint32_t cpre[kMaxScen + 1];
+    __shared__ double rec[kMaxScen][kPartial];
+    __shared__ double red[kBlock / kWave][kPartial];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        uint32_t a = 0;
+        for (int s = 0; s < n; ++s) {
+            cpre[s] = a;
+            const hw_scalars* sc = descs[s].scal;
+            const uint32_t nl = sc->done ? 0u : (uint32_t)sc->n_leaves;
+            a += (nl + kBlock - 1) / kBlock;
+        }
+        cpre[n] = a;
+    }
+    for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
+    __syncthreads();
+    const uint32_t total = cpre[n];
+    const uint32_t xcd = blockIdx.x & 7u;
+    const uint32_t rank = blockIdx.x >> 3;
+    const uint32_t g8 = gridDim.x >> 3;
+    const uint32_t seg = (total + 7u) / 8u;
+    const uint32_t c_begin = xcd * seg;
+    const uint32_t c_end = c_begin + seg < total ? c_begin + seg : total;
+
+    Acc acc;
+    acc_reset(acc);
+    int cs = -1;
+    int cur = 0;
+    double t = 0.0, dt = 0.0;
+    uint32_t nl = 0;
+    for (uint32_t ch = c_begin + rank; ch < c_end; ch += g8) {
+        int s = cs < 0 ? 0 : cs;
+        while (cpre[s + 1] <= ch) ++s;
+        if (s != cs) {
+            if (cs >= 0) acc_flush(acc, red, rec[cs]);
+            cs = s;
+            const hw_scalars* sc = descs[s].scal;
+            cur = (int)sc->cur;
+            t = sc->t;
+            dt = sc->dt;
+            nl = (uint32_t)sc->n_leaves;
+        }
+        const Desc& d = descs[s];
+        const uint32_t leaf = (ch - cpre[s]) * kBlock + tid;
+        if (leaf < nl) fv1_leaf<T>(d, cur, t, dt, d.leaves[leaf], acc);
+    }
+    if (cs >= 0) acc_flush(acc, red, rec[cs]);
+    for (int q = tid; q < n * kPartial; q += kBlock) {
+        const int s = q / kPartial;
+        descs[s].partials[(uint64_t)blockIdx.x * kPartial + q % kPartial] =
+            rec[s][q % kPartial];
+    }
+}
+
+// Copy-down for leaves coarser than the traversal groups: every group below
+// such a leaf copies the leaf's new value from its first finest descendant.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(Launch lc)
+{
+    uint32_t lb;
+    const int s = scen_of(lc, blockIdx.x, lb);
+    const Desc& d = lc.descs[s];
+    const hw_scalars* sc = d.scal;
+    if (sc->done) return;
+    const uint32_t g = lb * kBlock + threadIdx.x;
+    if (g >= (1u << (2 * d.group_level))) return;
+    const uint32_t src = d.big_src[g];
+    if (src == kNone) return;
+    const int L = d.L;
+    const int n = level_of(src);
+    const uint64_t f0 = (uint64_t)(src - (uint32_t)level_off(n)) << (2 * (L - n));
+    const int per = 1 << (2 * (L - d.group_level));
+    const uint64_t base = (uint64_t)g * per;
+    const int o = sc->cur ^ 1;
+    for (int v = 0; v < 3; ++v) {
+        T* a = reinterpret_cast<T*>(d.fine[o][v]);
+        const T val = a[f0];
+        for (int q = 0; q < per; ++q)
+            if (base + q != f0) a[base + q] = val;
+    }
+}
+
+// One workgroup per problem: combine the FV1 partial records, then advance
+// t, choose the next CFL timestep (capped at dt_max, shortened to hit
+// t_end), update s_max, mass and counters, and flip the finest set.
+__global__ __launch_bounds__(kBlock) void k_finalize(const Desc* descs,
+                                                     int fv1_grid)
+{
+    __shared__ double red[kBlock / kWave][kPartial];
+    const Desc& d = descs[blockIdx.x];
+    hw_scalars* sc = d.scal;
+    if (sc->done) return;
+    Acc a;
+    acc_reset(a);
+    for (int b = threadIdx.x; b < fv1_grid; b += blockDim.x)
+        acc_add_record(a, d.partials + (uint64_t)b * kPartial);
+    __shared__ double tot[kPartial];
+    if (threadIdx.x < kPartial) tot[threadIdx.x] = 0.0;
+    __syncthreads();
+    acc_flush(a, red, tot);
+    if (threadIdx.x == 0) {
+        const double tn = sc->t + sc->dt;
+        const double ms = tot[0];
+        const double dmin = d.dx < d.dy ? d.dx : d.dy;
+        double dtn;
+        if (ms > 0.0) {
+            dtn = d.cfl * dmin / ms;
+            dtn = dtn < d.dt_max ? dtn : d.dt_max;
+        } else {
+            dtn = d.dt_max;
+        }
+        const double rest = d.t_end - tn;
+        dtn = dtn < rest ? dtn : rest;
+        sc->t = tn;
+        sc->dt = dtn;
+        sc->maxspeed = ms;
+        sc->mass = tot[4];
+        sc->smax[0] = tot[1] > 1.0 ? tot[1] : 1.0;
+        sc->smax[1] = tot[2] > 1.0 ? tot[2] : 1.0;
+        sc->smax[2] = tot[3] > 1.0 ? tot[3] : 1.0;
+        sc->step += 1;
+        sc->leaf_updates += sc->n_leaves;
+        sc->clips += (uint64_t)tot[5];
+        if (tot[6] > 0.0 || !isfinite(ms)) sc->nonfinite |= 1u;
+        sc->cur ^= 1u;
+        sc->done = (tn < d.t_end) ? 0u : 1u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ingest: row-major FP64 inputs -> Morton finest set 0 and finest bed level,
+// with partial maxima, wave speed and mass for the scalars.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ingest(const Desc* dd,
+                                                   const double* h,
+                                                   const double* qx,
+                                                   const double* qy,
+                                                   const double* z)
+{
+    __shared__ double red[kBlock / kWave][kPartial];
+    __shared__ double rec[kPartial];
+    const Desc& d = *dd;
+    const int L = d.L;
+    const uint64_t N = 1ull << (2 * L);
+    const uint32_t S = 1u << L;
+    const T g = (T)d.g, tol = (T)d.h_tol;
+    T* fh = reinterpret_cast<T*>(d.fine[0][0]);
+    T* fqx = reinterpret_cast<T*>(d.fine[0][1]);
+    T* fqy = reinterpret_cast<T*>(d.fine[0][2]);
+    double* zl = d.zhier + level_off(L);
+    Acc a;
+    acc_reset(a);
+    for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < N;
+         f += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = compact1by1((uint32_t)f), j = compact1by1((uint32_t)f >> 1);
+        const uint64_t r = (uint64_t)j * S + i;
+        const double hv = h[r], xv = qx[r], yv = qy[r], zv = z[r];
+        if (!(hv >= 0.0) || !isfinite(hv) || !isfinite(xv) || !isfinite(yv) ||
+            !isfinite(zv))
+            a.v[6] = 2.0;
+        const T th = (T)hv, tx = (T)xv, ty = (T)yv;
+        fh[f] = th;
+        fqx[f] = tx;
+        fqy[f] = ty;
+        zl[f] = zv;
+        acc_max(a, 0, wave_speed<T>(th, tx, ty, g, tol));
+        acc_max(a, 1, fabs((double)th));
+        acc_max(a, 2, fabs((double)tx));
+        acc_max(a, 3, fabs((double)ty));
+        a.v[4] += ((double)th * d.dx) * d.dy;
+        acc_max(a, 7, fabs(zv));
+    }
+    if (threadIdx.x < kPartial) rec[threadIdx.x] = 0.0;
+    __syncthreads();
+    acc_flush(a, red, rec);
+    if (threadIdx.x < kPartial)
+        d.partials[(uint64_t)blockIdx.x * kPartial + threadIdx.x] = rec[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_ingest_final(const Desc* dd, int grid)
+{
+    __shared__ double red[kBlock / kWave][kPartial];
+    __shared__ double tot[kPartial];
+    const Desc& d = *dd;
+    hw_scalars* sc = d.scal;
+    Acc a;
+    acc_reset(a);
+    for (int b = threadIdx.x; b < grid; b += blockDim.x)
+        acc_add_record(a, d.partials + (uint64_t)b * kPartial);
+    if (threadIdx.x < kPartial) tot[threadIdx.x] = 0.0;
+    __syncthreads();
+    acc_flush(a, red, tot);
+    if (threadIdx.x == 0) {
+        const double ms = tot[0];
+        const double dmin = d.dx < d.dy ? d.dx : d.dy;
+        double dt;
+        if (ms > 0.0) {
+            dt = d.cfl * dmin / ms;
+            dt = dt < d.dt_max ? dt : d.dt_max;
+        } else {
+            dt = d.dt_max;
+        }
+        const double rest = d.t_end - 0.0;
+        dt = dt < rest ? dt : rest;
+        sc->t = 0.0;
+        sc->dt = dt;
+        sc->mass = tot[4];
+        sc->mass0 = tot[4];
+        sc->smax[0] = tot[1] > 1.0 ? tot[1] : 1.0;
+        sc->smax[1] = tot[2] > 1.0 ? tot[2] : 1.0;
+        sc->smax[2] = tot[3] > 1.0 ? tot[3] : 1.0;
+        sc->smax[3] = tot[7] > 1.0 ? tot[7] : 1.0;
+        sc->maxspeed = ms;
+        for (int q = 0; q < 6; ++q) sc->acc[q] = 0.0;
+        sc->step = 0;
+        sc->n_leaves = 0;
+        sc->leaf_updates = 0;
+        sc->clips = 0;
+        sc->cur = 0;
+        sc->done = (0.0 < d.t_end) ? 0u : 1u;
+        sc->nonfinite = tot[6] > 0.0 ? 2u : 0u;
+        sc->pad = 0;
+    }
+}
+
+// Current finest set -> row-major FP64.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_export(const Desc* dd, double* h,
+                                                   double* qx, double* qy)
+{
+    const Desc& d = *dd;
+    const int L = d.L;
+    const uint64_t N = 1ull << (2 * L);
+    const uint32_t S = 1u << L;
+    const int cur = (int)d.scal->cur;
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = (uint32_t)(r % S), j = (uint32_t)(r / S);
+        const uint32_t f = morton(i, j);
+        if (h) h[r] = (double)reinterpret_cast<const T*>(d.fine[cur][0])[f];
+        if (qx) qx[r] = (double)reinterpret_cast<const T*>(d.fine[cur][1])[f];
+        if (qy) qy[r] = (double)reinterpret_cast<const T*>(d.fine[cur][2])[f];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers (used by the C ABI layer)
+// ---------------------------------------------------------------------------
+
+hipError_t launch_set_desc(const Desc& d, Desc* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, s, d, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_ingest(int prec, const Desc* dd, uint32_t grid,
+                         const double* h, const double* qx, const double* qy,
+                         const double* z, hipStream_t s)
+{
+    if (prec == HW_FP64)
+        hipLaunchKernelGGL(k_ingest<double>, dim3(grid), dim3(kBlock), 0, s, dd, h, qx, qy, z);
+    else
+        hipLaunchKernelGGL(k_ingest<float>, dim3(grid), dim3(kBlock), 0, s, dd, h, qx, qy, z);
+    hipLaunchKernelGGL(k_ingest_final, dim3(1), dim3(kBlock), 0, s, dd, (int)grid);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_bed(Launch lc, uint32_t nblocks, int pass, int tl,
+                             int cpt, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_encode<double, 1, false, false>), dim3(nblocks),
+                       dim3(kBlock), 0, s, lc, pass, tl, cpt, (double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_flow(int prec, Launch lc, uint32_t nblocks, int pass,
+                              int tl, int cpt, double* details, hipStream_t s)
+{
+    if (prec == HW_FP64) {
+        if (details)
+            hipLaunchKernelGGL((k_encode<double, 3, true, true>), dim3(nblocks),
+                               dim3(kBlock), 0, s, lc, pass, tl, cpt, details);
+        else
+            hipLaunchKernelGGL((k_encode<double, 3, true, false>), dim3(nblocks),
+                               dim3(kBlock), 0, s, lc, pass, tl, cpt, details);
+    } else {
+        if (details)
+            hipLaunchKernelGGL((k_encode<float, 3, true, true>), dim3(nblocks),
+                               dim3(kBlock), 0, s, lc, pass, tl, cpt, details);
+        else
+            hipLaunchKernelGGL((k_encode<float, 3, true, false>), dim3(nblocks),
+                               dim3(kBlock), 0, s, lc, pass, tl, cpt, details);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_only(int prec, Launch lc, uint32_t nblocks, hipStream_t s)
+{
+    if (prec == HW_FP64)
+        hipLaunchKernelGGL(k_flag_only<double>, dim3(nblocks), dim3(kBlock), 0, s, lc);
+    else
+        hipLaunchKernelGGL(k_flag_only<float>, dim3(nblocks), dim3(kBlock), 0, s, lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_regularise(Launch lc, uint32_t nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_regularise, dim3(nblocks), dim3(kBlock), 0, s, lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_traverse(Launch lc, uint32_t nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_traverse<false>, dim3(nblocks), dim3(kBlock), 0, s, lc);
+    hipLaunchKernelGGL(k_trav_scan, dim3(lc.n), dim3(1024), 0, s, lc.descs);
+    hipLaunchKernelGGL(k_traverse<true>, dim3(nblocks), dim3(kBlock), 0, s, lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
+                           hipStream_t s)
+{
+    if (prec == HW_FP64)
+        hipLaunchKernelGGL(k_fv1<double>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+    else
+        hipLaunchKernelGGL(k_fv1<float>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, hipStream_t s)
+{
+    if (prec == HW_FP64)
+        hipLaunchKernelGGL(k_fill<double>, dim3(fill_blocks), dim3(kBlock), 0, s, fill);
+    else
+        hipLaunchKernelGGL(k_fill<float>, dim3(fill_blocks), dim3(kBlock), 0, s, fill);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(n), dim3(kBlock), 0, s, descs, (int)grid);
+    return hipGetLastError();
+}
+
+hipError_t launch_fv1(int prec, const Desc* descs, int n, uint32_t grid,
+                      Launch fill, uint32_t fill_blocks, hipStream_t s)
+{
+    hipError_t e = launch_fv1_only(prec, descs, n, grid, s);
+    if (e == hipSuccess) e = launch_fill(prec, fill, fill_blocks, s);
+    if (e == hipSuccess) e = launch_finalize(descs, n, grid, s);
+    return e;
+}
+
+hipError_t launch_export(int prec, const Desc* dd, uint64_t N, double* h,
+                         double* qx, double* qy, hipStream_t s)
+{
+    uint64_t blocks = (N + kBlock - 1) / kBlock;
+    if (blocks > 65536) blocks = 65536;
+    if (prec == HW_FP64)
+        hipLaunchKernelGGL(k_export<double>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, dd, h, qx, qy);
+    else
+        hipLaunchKernelGGL(k_export<float>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, dd, h, qx, qy);
+    return hipGetLastError();
+}
+
+}  // namespace hw

@@ -1,0 +1,103 @@
+"""The C-ABI library loads and exports every symbol include/hwfv1.h declares;
+host-side validation behaves as documented.  No GPU work is launched."""
+import ctypes as C
+import math
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parent.parent
+HEADER = ROOT / "include" / "hwfv1.h"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(
+        r"^\s*(?:const\s+)?(?:int|void|size_t|uint64_t|char)\s*\**\s*(\w+)\s*\(",
+        text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("mra_encode", "mra_flag", "mra_traverse_leaves", "fv1_step",
+                     "hwfv1_run", "hwfv1_run_batch", "hw_ingest", "hw_export",
+                     "hw_plan_create", "hw_plan_destroy", "hw_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2206_05761_amd as hw
+    lib = C.CDLL(str(hw.LIB_PATH))
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _params(**kw):
+    p = dict(L=6, eps=1e-3, dx=1 / 64, dt_max=0.01, bc=("wall",) * 4)
+    p.update(kw)
+    return p
+
+
+def test_validation_accepts_and_rejects():
+    import paper_2206_05761_amd as hw
+    hw.validate(hw.make_problem(_params()))
+    hw.validate(hw.make_problem(_params(), "fp32_bulk"))
+    bad = [dict(L=0), dict(L=15), dict(eps=-1.0), dict(eps=math.nan),
+           dict(dx=0.0), dict(cfl=1.5), dict(dt_max=0.0), dict(h_tol=-1.0),
+           dict(manning_n=-0.1), dict(t_end=0.0), dict(bc=(0, 1, 2, 0)),
+           dict(q_peak=1.0, t_peak=10.0, t_base=5.0, inlet_y0=0.0, inlet_y1=1.0),
+           dict(q_peak=1.0, t_peak=1.0, t_base=2.0, inlet_y0=1.0, inlet_y1=1.0)]
+    for b in bad:
+        with pytest.raises(hw.HwError) as e:
+            hw.validate(hw.make_problem(_params(**b)))
+        assert e.value.code == hw.HW_EINVAL
+    p = hw.make_problem(_params())
+    p.precision = 7
+    with pytest.raises(hw.HwError):
+        hw.validate(p)
+
+
+def test_sizes_and_workspace():
+    import paper_2206_05761_amd as hw
+    for L in (1, 2, 6, 12, 14):
+        assert hw.n_fine(L) == 4 ** L
+        assert hw.n_coarse(L) == (4 ** L - 1) // 3
+        assert hw.n_hier(L) == (4 ** (L + 1) - 1) // 3
+    w6 = hw.workspace_bytes(hw.make_problem(_params(L=6)))
+    w12 = hw.workspace_bytes(hw.make_problem(_params(L=12)))
+    assert w6 > 0 and w12 > w6 and w12 % 256 == 0
+
+
+def test_null_and_misaligned_buffers_are_rejected_before_launch():
+    import paper_2206_05761_amd as hw
+    p = hw.make_problem(_params())
+    b = hw.HwBuffers()
+    rc = hw.lib().mra_encode(C.byref(p), C.byref(b), None, None)
+    assert rc == hw.HW_EINVAL
+    assert b"NULL" in hw.lib().hw_last_error()
+    for s in range(2):
+        for v in range(3):
+            b.fine[s][v] = 4096 * (1 + s * 3 + v)
+    for v in range(3):
+        b.coarse[v] = 65536 + 4096 * v
+    b.zhier, b.zsig, b.raw, b.sig = 1 << 20, 2 << 20, 3 << 20, 4 << 20
+    b.leaves, b.scal, b.work = 5 << 20, 6 << 20, (7 << 20) + 8
+    b.work_bytes = 1 << 30
+    rc = hw.lib().fv1_step(C.byref(p), C.byref(b), None)
+    assert rc == hw.HW_EINVAL and b"aligned" in hw.lib().hw_last_error()
+    b.work = 7 << 20
+    b.work_bytes = 16
+    rc = hw.lib().mra_flag(C.byref(p), C.byref(b), None)
+    assert rc == hw.HW_ECAPACITY
+
+
+def test_plan_rejects_bad_counts_without_gpu():
+    import paper_2206_05761_amd as hw
+    h = C.c_void_p()
+    rc = hw.lib().hw_plan_create(C.byref(h), None, None, 0, None)
+    assert rc == hw.HW_EINVAL
+    rc = hw.lib().hw_plan_create(C.byref(h), None, None, 65, None)
+    assert rc == hw.HW_EINVAL

@@ -311,6 +311,24 @@ def test_inflow_volume_matches_hydrograph_integral():
     assert n > 10
 
 
+def test_hydrograph_workload_stores_the_delivered_volume():
+    """The hydrograph workload (closed inflow edge, other edges open) at a
+    small L: while no water has reached an open edge the stored volume is
+    the delivered hydrograph volume, within the left-Riemann-sum error of
+    the explicit source (the rising limb is under-counted, never over)."""
+    w = W.hydrograph_l12(L=7)
+    p = dict(w.params, t_end=1500.0)
+    o = O.Oracle(p, w.h, w.qx, w.qy, w.z)
+    o.run(100_000)
+    s = o.scalars()
+    t = s["t"]
+    assert t == 1500.0
+    delivered = 0.5 * w.params["q_peak"] * t * t / w.params["t_peak"]
+    bound = t * w.params["dt_max"] * (w.params["q_peak"] / w.params["t_peak"]) / 2
+    assert delivered - bound <= s["mass"] <= delivered * (1 + 1e-12)
+    assert s["clips"] == 0
+
+
 # --------------------------------------------------------------------------
 # Timestep and checkpoint/resume
 # --------------------------------------------------------------------------

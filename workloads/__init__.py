@@ -14,7 +14,8 @@ Workloads (square 2^L x 2^L grids):
                            0.035, open boundaries, 500 steps
   hydrograph_l12           10 x 10 km, fractal bed (relief 50 m), dry start,
                            triangular west-edge inflow (500 m^3/s peak at
-                           1800 s, base 3600 s), Manning 0.035, 2000 steps
+                           1800 s, base 3600 s) through a closed west edge,
+                           other edges open, Manning 0.035, 2000 steps
   ensemble_64              64 members with L in {8..11}, eps in
                            {1e-4, 1e-3, 1e-2}, own fractal bed (relief 5-50 m),
                            dam-break or hydrograph forcing, Manning U(0.01,
@@ -135,7 +136,11 @@ def circular_dambreak_l10(seed: int = 2, L: int = 10,
 def hydrograph_l12(seed: int = 3, L: int = 12, n_steps: int = 2000,
                    relief: float = 50.0, q_peak: float = 500.0) -> Workload:
     length = 10_000.0
-    p = base_params(L, length, 1e-3, manning_n=0.035, bc=("open",) * 4,
+    # The inflow edge is closed: the hydrograph is the only water entering
+    # there (a zero-gradient copy would import water wherever the inflow
+    # pushes the flow away from the edge).
+    p = base_params(L, length, 1e-3, manning_n=0.035,
+                    bc=("wall", "open", "open", "open"),
                     inlet_y0=4500.0, inlet_y1=5500.0, q_peak=q_peak,
                     t_peak=1800.0, t_base=3600.0)
     z = fractal_bed(L, relief, seed)
@@ -175,7 +180,8 @@ def ensemble_member(i: int, n_steps: int = 1000, levels=(8, 9, 10, 11),
         r = np.sqrt((x - 500.0) ** 2 + (y - 500.0) ** 2)
         h = np.where(r < 100.0, 5.0, 0.0)
     else:
-        p = base_params(L, length, eps, manning_n=n_m, bc=("open",) * 4,
+        p = base_params(L, length, eps, manning_n=n_m,
+                        bc=("wall", "open", "open", "open"),
                         inlet_y0=450.0, inlet_y1=550.0, q_peak=50.0,
                         t_peak=1800.0, t_base=3600.0)
         h = zero.copy()
