@@ -214,6 +214,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB three "
+                         "times (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -275,6 +278,15 @@ def main():
     if not args.no_batch:
         line["batched"] = bench_batch(hw, args.batch_steps, args.warmup,
                                       args.batch_members)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = {"read": n * 8, "write": n * 8}
+        del src, dst
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(line), flush=True)

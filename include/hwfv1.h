@@ -147,8 +147,10 @@ typedef struct hw_scalars {
  *   sig         significance after regularisation, (N-1)/3 bytes
  *   leaves      leaf list, capacity N uint32
  *   scal        one hw_scalars record
- *   work        scratch of hw_workspace_bytes() bytes; its content is
- *               private to the library and carries nothing between calls
+ *   work        scratch of hw_workspace_bytes() bytes, private to the
+ *               library; between mra_traverse_leaves and fv1_step it carries
+ *               the traversal's fill table and the per-finest-cell leaf
+ *               level map (N bytes) that the FV1 neighbour lookup reads
  */
 typedef struct hw_buffers {
     void* fine[2][3];
@@ -166,9 +168,12 @@ typedef struct hw_buffers {
 /* Launch-shape choices (all have defaults; see hw_default_tuning). */
 typedef struct hw_tuning {
     int32_t encode_cells_per_thread; /* 4 or 16 finest cells per thread in
-                                        the first encoding pass            */
-    int32_t fv1_block;               /* FV1 workgroup size: 64..1024       */
-    int32_t fv1_grid;                /* FV1 persistent workgroups (0: auto) */
+                                        each encoding pass (5 or 6 levels) */
+    int32_t fv1_block;               /* reserved (FV1 workgroups are 256)  */
+    int32_t fv1_grid;                /* FV1 persistent workgroups, 8..8192,
+                                        0 = automatic                      */
+    int32_t fv1_min_waves;           /* FV1 occupancy request: 0 (compiler
+                                        choice), 5, 6 or 8 waves per SIMD  */
 } hw_tuning;
 
 typedef struct hw_plan hw_plan;
@@ -254,7 +259,9 @@ int mra_traverse_leaves(const hw_problem* p, const hw_buffers* b,
  * hydrostatically reconstructed HLL fluxes, forward Euler with timestep
  * hw_scalars.dt, rain, inflow, positivity clip, dry-cell discharge reset and
  * point-implicit Manning friction.  The new value is written to all finest
- * descendants of the leaf in the other finest set; then t += dt, the next
+ * descendants of the leaf in the other finest set (leaves coarser than
+ * level L-2 write their first descendant and a fill kernel copies it to the
+ * rest); then t += dt, the next
  * CFL timestep, s_max, mass and counters are updated and cur flips.  Does
  * nothing once hw_scalars.done is set.  Requires the leaf list and the
  * encoding of the same state.

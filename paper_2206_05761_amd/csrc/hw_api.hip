@@ -32,7 +32,7 @@ hipError_t launch_fv1(int prec, const Desc* descs, int n, uint32_t grid,
 hipError_t launch_export(int prec, const Desc* dd, uint64_t N, double* h,
                          double* qx, double* qy, hipStream_t s);
 hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
-                           hipStream_t s);
+                           int waves, hipStream_t s);
 hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, hipStream_t s);
 hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t s);
 }  // namespace hw
@@ -71,6 +71,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int group_level(int L) { return L >= 2 ? L - 2 : 0; }
+uint64_t hw_n_fine_(int L) { return 1ull << (2 * L); }
 uint64_t n_groups(int L) { return 1ull << (2 * group_level(L)); }
 uint32_t n_trav(int L) { return (uint32_t)((n_groups(L) + hw::kBlock - 1) / hw::kBlock); }
 uint32_t n_coarse_blocks(int L)
@@ -90,7 +91,7 @@ uint32_t encode_blocks(int L, int pass, int tl)
 }
 
 struct WorkLayout {
-    size_t desc, tcount, big_src, partials, total;
+    size_t desc, tcount, big_src, lmap, partials, total;
 };
 
 WorkLayout work_layout(int L)
@@ -103,6 +104,8 @@ WorkLayout work_layout(int L)
     o = align_up(o + (n_trav(L) + 1) * sizeof(uint32_t));
     w.big_src = o;
     o = align_up(o + n_groups(L) * sizeof(uint32_t));
+    w.lmap = o;
+    o = align_up(o + (size_t)hw_n_fine_(L));
     w.partials = o;
     o = align_up(o + (size_t)hw::kMaxFv1Grid * hw::kPartial * sizeof(double));
     w.total = o;
@@ -209,6 +212,7 @@ Desc make_desc(const hw_problem* p, const hw_buffers* b, double* partials)
     char* wk = static_cast<char*>(b->work);
     d.tcount = reinterpret_cast<uint32_t*>(wk + w.tcount);
     d.big_src = reinterpret_cast<uint32_t*>(wk + w.big_src);
+    d.lmap = reinterpret_cast<uint8_t*>(wk + w.lmap);
     d.partials = partials ? partials : reinterpret_cast<double*>(wk + w.partials);
     d.ntrav = n_trav(p->L);
     return d;
@@ -250,7 +254,6 @@ int prep_single(const hw_problem* p, const hw_buffers* b, hipStream_t s,
     return HW_OK;
 }
 
-int default_cpt(int L) { return L >= 10 ? 2 : 1; }
 
 }  // namespace
 
@@ -263,6 +266,7 @@ struct hw_plan {
     int precision = 0;
     int tl = 5, cp = 1;
     uint32_t fv1_grid = 8;
+    int fv1_waves = 0;
     std::vector<hw_problem> problems;
     std::vector<hw_buffers> buffers;
     std::vector<Desc> host_desc;
@@ -307,7 +311,8 @@ hipError_t enqueue_phase(hw_plan* pl, int phase, hipStream_t s)
         e = hw::launch_traverse(Launch{pl->d_desc, pl->trav_prefix, n}, pl->trav_blocks, s);
         break;
     case HW_PH_FV1:
-        e = hw::launch_fv1_only(pl->precision, pl->d_desc, n, pl->fv1_grid, s);
+        e = hw::launch_fv1_only(pl->precision, pl->d_desc, n, pl->fv1_grid,
+                                pl->fv1_waves, s);
         break;
     case HW_PH_FILL:
         e = hw::launch_fill(pl->precision, Launch{pl->d_desc, pl->trav_prefix, n},
@@ -449,9 +454,11 @@ void hw_default_tuning(const hw_problem* p, hw_tuning* out)
 {
     if (!out) return;
     const int L = p && p->L >= 1 && p->L <= HW_MAX_L ? p->L : 10;
-    out->encode_cells_per_thread = default_cpt(L) == 2 ? 16 : 4;
+    const bool fp32 = p && p->precision == HW_FP32_BULK;
+    out->encode_cells_per_thread = (fp32 && L >= 10) ? 16 : 4;
     out->fv1_block = hw::kBlock;
     out->fv1_grid = 0;
+    out->fv1_min_waves = 0;
 }
 
 int hw_ingest(const hw_problem* p, const hw_buffers* b, const double* h,
@@ -486,7 +493,9 @@ int mra_encode(const hw_problem* p, const hw_buffers* b, double* details,
     if (details && ((uintptr_t)details % 8))
         return fail(HW_EINVAL, "details must be 8-byte aligned");
     const Desc* dd = work_desc(b);
-    const int cp = default_cpt(p->L), tl = pass_levels(cp);
+    hw_tuning tu;
+    hw_default_tuning(p, &tu);
+    const int cp = tu.encode_cells_per_thread == 16 ? 2 : 1, tl = pass_levels(cp);
     for (int k = 0; k < n_passes(p->L, tl); ++k) {
         hipError_t e = hw::launch_encode_flow(p->precision, Launch{dd, nullptr, 1},
                                               encode_blocks(p->L, k, tl), k, tl, cp,
@@ -595,8 +604,15 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
             return fail(HW_EINVAL, "fv1_grid must be in 0..%d", hw::kMaxFv1Grid);
         }
         tu.fv1_grid = tuning->fv1_grid;
+        if (tuning->fv1_min_waves != 0 && tuning->fv1_min_waves != 5 &&
+            tuning->fv1_min_waves != 6 && tuning->fv1_min_waves != 8) {
+            delete pl;
+            return fail(HW_EINVAL, "fv1_min_waves must be 0, 5, 6 or 8");
+        }
+        tu.fv1_min_waves = tuning->fv1_min_waves;
     }
     pl->cp = tu.encode_cells_per_thread == 16 ? 2 : 1;
+    pl->fv1_waves = tu.fv1_min_waves;
     pl->tl = pass_levels(pl->cp);
     pl->fv1_grid = tu.fv1_grid > 0 ? (uint32_t)((tu.fv1_grid + 7) / 8 * 8)
                                    : default_fv1_grid(max_leaves);

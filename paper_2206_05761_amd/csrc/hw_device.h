@@ -33,6 +33,7 @@ struct Desc {
     hw_scalars* scal;
     uint32_t* tcount;      // traversal workgroup counts / offsets
     uint32_t* big_src;     // per group: leaf index of a coarser leaf or kNone
+    uint8_t* lmap;         // per finest cell: level of the leaf containing it
     double* partials;      // FV1 / ingest partial records, kPartial each
     uint32_t ntrav;        // traversal workgroups of this problem
     uint32_t pad1;
@@ -84,7 +85,32 @@ __device__ inline int level_of(uint32_t idx)
     return (31 - __clz(3u * idx + 1u)) >> 1;
 }
 
-// Problem of workgroup b and the workgroup's index inside that problem.
+// Global-address-space view of a pointer: loads and stores through it are
+// global (not flat) instructions, with the base in SGPRs when uniform.
+template <typename T>
+using gp = T __attribute__((address_space(1)))*;
+
+// Native vector types (usable through global pointers).
+typedef double vd2 __attribute__((ext_vector_type(2)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ inline gp<T> glob(T* p)
+{
+    return (gp<T>)p;
+}
+
+// Make a value the compiler cannot prove wave-uniform, but that is, live in
+// an SGPR (so descriptor reads through it become scalar loads).
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint32_t uniform(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Problem of workgroup b and the workgroup's index inside that problem
+// (both uniform over the workgroup).
 __device__ inline int scen_of(const Launch& l, uint32_t b, uint32_t& local)
 {
     if (!l.prefix) {
@@ -97,7 +123,8 @@ __device__ inline int scen_of(const Launch& l, uint32_t b, uint32_t& local)
         if (l.prefix[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    local = b - l.prefix[lo];
+    lo = uniform(lo);
+    local = uniform(b - l.prefix[lo]);
     return lo;
 }
 

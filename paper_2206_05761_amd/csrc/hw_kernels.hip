@@ -63,19 +63,19 @@ __device__ inline bool significant(const Haar& h, double smax, double thr)
     return (m / smax) >= thr;
 }
 
-__device__ inline void load4(const double* p, double o[4])
+__device__ inline void load4(gp<const double> p, double o[4])
 {
-    double2 a = *reinterpret_cast<const double2*>(p);
-    double2 b = *reinterpret_cast<const double2*>(p + 2);
+    const vd2 a = *reinterpret_cast<gp<const vd2>>(p);
+    const vd2 b = *reinterpret_cast<gp<const vd2>>(p + 2);
     o[0] = a.x;
     o[1] = a.y;
     o[2] = b.x;
     o[3] = b.y;
 }
 
-__device__ inline void load4(const float* p, double o[4])
+__device__ inline void load4(gp<const float> p, double o[4])
 {
-    float4 a = *reinterpret_cast<const float4*>(p);
+    const vf4 a = *reinterpret_cast<gp<const vf4>>(p);
     o[0] = a.x;
     o[1] = a.y;
     o[2] = a.z;
@@ -114,31 +114,35 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     const int tid = threadIdx.x;
     const uint64_t ncoarse = level_off(L);
 
-    const T* src[NV];
+    const int cur = uniform((int)sc->cur);
+    gp<const T> src[NV];
+    gp<T> dstb[NV];
     double smax[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         if (FLOW) {
             src[v] = pass == 0
-                         ? reinterpret_cast<const T*>(d.fine[sc->cur][v])
-                         : reinterpret_cast<const T*>(d.coarse[v]) +
+                         ? glob(reinterpret_cast<const T*>(d.fine[cur][v]))
+                         : glob(reinterpret_cast<const T*>(d.coarse[v])) +
                                level_off(n_in);
+            dstb[v] = glob(reinterpret_cast<T*>(d.coarse[v]));
             smax[v] = sc->smax[v];
         } else {
-            src[v] = reinterpret_cast<const T*>(d.zhier + level_off(n_in));
+            src[v] = glob(reinterpret_cast<const T*>(d.zhier)) + level_off(n_in);
+            dstb[v] = glob(reinterpret_cast<T*>(d.zhier));
             smax[v] = sc->smax[3];
         }
     }
-    uint8_t* flags = FLOW ? d.raw : d.zsig;
+    const gp<uint8_t> flags = glob(FLOW ? d.raw : d.zsig);
+    const gp<const uint8_t> zsig = glob(static_cast<const uint8_t*>(d.zsig));
+    const gp<double> det = glob(details);
+    const double eps = d.eps;
 
-    auto dst_of = [&](int v, int n) -> T* {
-        if (FLOW) return reinterpret_cast<T*>(d.coarse[v]) + level_off(n);
-        return reinterpret_cast<T*>(d.zhier + level_off(n));
-    };
+    auto dst_of = [&](int v, int n) -> gp<T> { return dstb[v] + level_off(n); };
 
     // Encode one cell (n, k) from its four children, store it, flag it.
     auto emit = [&](int n, uint64_t k, const double (*ch)[4], double* out) {
-        const double thr = ldexp(d.eps, n - L);
+        const double thr = ldexp(eps, n - L);
         bool f = false;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -149,14 +153,14 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
             if (significant(hh, smax[v], thr)) f = true;
             if (DET) {
                 const uint64_t o = level_off(n) + k;
-                details[(uint64_t)(v * 3 + 0) * ncoarse + o] = hh.da;
-                details[(uint64_t)(v * 3 + 1) * ncoarse + o] = hh.db;
-                details[(uint64_t)(v * 3 + 2) * ncoarse + o] = hh.dg;
+                det[(uint64_t)(v * 3 + 0) * ncoarse + o] = hh.da;
+                det[(uint64_t)(v * 3 + 1) * ncoarse + o] = hh.db;
+                det[(uint64_t)(v * 3 + 2) * ncoarse + o] = hh.dg;
             }
         }
         const uint64_t o = level_off(n) + k;
         uint8_t fl = f ? 1 : 0;
-        if (FLOW) fl |= d.zsig[o];
+        if (FLOW) fl |= zsig[o];
         flags[o] = fl ? 1 : 0;
     };
 
@@ -165,6 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     double p[NV];
     if ((uint32_t)tid < M) {
         const uint64_t tile_in = (uint64_t)b << (2 * lv);
+        // All child loads are issued before any store of this thread.
         if (cp == 1) {
             const uint64_t base = tile_in + 4ull * tid;
             double ch[NV][4];
@@ -172,24 +177,29 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
             for (int v = 0; v < NV; ++v) {
                 if (FLOW && pass == 0) load4(src[v] + base, ch[v]);
                 else
+#pragma unroll
                     for (int q = 0; q < 4; ++q) ch[v][q] = (double)src[v][base + q];
             }
             emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + tid, ch, p);
         } else {
             const uint64_t base = tile_in + 16ull * tid;
-            double mid[NV][4];
-            for (int qq = 0; qq < 4; ++qq) {
-                double ch[NV][4];
+            double ch[4][NV][4];
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    if (FLOW && pass == 0) load4(src[v] + base + 4 * qq, ch[v]);
+                    if (FLOW && pass == 0) load4(src[v] + base + 4 * qq, ch[qq][v]);
                     else
+#pragma unroll
                         for (int q = 0; q < 4; ++q)
-                            ch[v][q] = (double)src[v][base + 4 * qq + q];
+                            ch[qq][v][q] = (double)src[v][base + 4 * qq + q];
                 }
+            double mid[NV][4];
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
                 double o[NV];
                 emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + 4ull * tid + qq,
-                     ch, o);
+                     ch[qq], o);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) mid[v][qq] = o[v];
             }
@@ -269,13 +279,13 @@ __global__ __launch_bounds__(kBlock) void k_regularise(Launch lc)
     const uint32_t k = (uint32_t)(c - level_off(n));
     const uint32_t i = compact1by1(k), j = compact1by1(k >> 1);
     const uint32_t S = 1u << n;
-    const uint8_t* raw = d.raw + level_off(n);
+    const gp<const uint8_t> raw = glob(static_cast<const uint8_t*>(d.raw)) + level_off(n);
     uint8_t f = raw[k];
     if (i > 0) f |= raw[morton(i - 1, j)];
     if (i + 1 < S) f |= raw[morton(i + 1, j)];
     if (j > 0) f |= raw[morton(i, j - 1)];
     if (j + 1 < S) f |= raw[morton(i, j + 1)];
-    d.sig[c] = f ? 1 : 0;
+    glob(d.sig)[c] = f ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -290,19 +300,41 @@ __global__ __launch_bounds__(kBlock) void k_regularise(Launch lc)
 // levels below g.  Leaves come out in ascending first-descendant order.
 
 template <bool WRITE>
-__device__ inline int walk_group(const Desc& d, uint32_t g, uint32_t* out,
-                                 uint32_t& big)
+__device__ inline int walk_group(const Desc& d, uint32_t g, gp<uint32_t> out,
+                                 uint32_t& big, uint32_t lvl[4])
 {
     const int L = d.L;
     const int Lg = d.group_level;
-    const uint8_t* sig = d.sig;
+    const gp<const uint8_t> sig = glob(static_cast<const uint8_t*>(d.sig));
+    // Flags of every cell on the root-to-g path (levels 0..Lg) and of the
+    // four children of g, all loaded before any decision: the walk then
+    // costs one memory round trip instead of one per level.
+    uint8_t pf[HW_MAX_L];
+#pragma unroll
+    for (int n = 0; n < HW_MAX_L; ++n) {
+        const int nn = n < Lg ? n : Lg;   // levels past Lg repeat Lg (in bounds)
+        pf[n] = sig[level_off(nn) + (g >> (2 * (Lg - nn)))];
+    }
+    const int n1 = Lg + 1;
+    const int nk = n1 < L ? n1 : Lg;      // in-bounds stand-in when n1 == L
+    const uint64_t kb = n1 < L ? level_off(n1) + 4ull * g : level_off(Lg) + g;
+    uint8_t kf[4];
+#pragma unroll
+    for (int c1 = 0; c1 < 4; ++c1) kf[c1] = sig[n1 < L ? kb + c1 : kb];
+    (void)nk;
+    uint32_t path = 0;
+#pragma unroll
+    for (int n = 0; n < HW_MAX_L; ++n)
+        if (n <= Lg && pf[n]) path |= 1u << n;
+    uint32_t kids = 0;
+    if (n1 < L) {
+#pragma unroll
+        for (int c1 = 0; c1 < 4; ++c1)
+            if (kf[c1]) kids |= 1u << c1;
+    }
     int cnt = 0;
     big = kNone;
-    int n = 0;
-    for (; n < Lg; ++n) {
-        const uint32_t k = g >> (2 * (Lg - n));
-        if (!sig[level_off(n) + k]) break;
-    }
+    const int n = __ffs(~path) - 1;   // first insignificant level on the path
     if (n < Lg) {
         const uint32_t k = g >> (2 * (Lg - n));
         const uint32_t idx = (uint32_t)level_off(n) + k;
@@ -311,26 +343,45 @@ __device__ inline int walk_group(const Desc& d, uint32_t g, uint32_t* out,
             if (WRITE) out[cnt] = idx;
             ++cnt;
         }
+        lvl[0] = lvl[1] = lvl[2] = lvl[3] = (uint32_t)n;
         return cnt;
     }
-    if (!sig[level_off(Lg) + g]) {
+    if (n == Lg) {
         if (WRITE) out[cnt] = (uint32_t)level_off(Lg) + g;
+        lvl[0] = lvl[1] = lvl[2] = lvl[3] = (uint32_t)Lg;
         return cnt + 1;
     }
-    const int n1 = Lg + 1;
     for (uint32_t c1 = 0; c1 < 4; ++c1) {
         const uint32_t k1 = 4 * g + c1;
-        if (n1 == L || !sig[level_off(n1) + k1]) {
+        if (!((kids >> c1) & 1u)) {
             if (WRITE) out[cnt] = (uint32_t)level_off(n1) + k1;
             ++cnt;
+            lvl[c1] = (uint32_t)n1;
         } else {
             for (uint32_t c2 = 0; c2 < 4; ++c2) {
                 if (WRITE) out[cnt] = (uint32_t)level_off(n1 + 1) + 4 * k1 + c2;
                 ++cnt;
             }
+            lvl[c1] = (uint32_t)(n1 + 1);
         }
     }
     return cnt;
+}
+
+// Leaf levels of the finest cells of group g: 4^(L-Lg) bytes (16, or 4 when
+// L = 1); within each quarter of the group the four values are equal.
+__device__ inline void write_level_map(const Desc& d, uint32_t g, const uint32_t lvl[4])
+{
+    const int per = 1 << (2 * (d.L - d.group_level));
+    if (per == 16) {
+        const vu4 v = {lvl[0] * 0x01010101u, lvl[1] * 0x01010101u,
+                       lvl[2] * 0x01010101u, lvl[3] * 0x01010101u};
+        *reinterpret_cast<gp<vu4>>(glob(d.lmap) + 16ull * g) = v;
+    } else {
+        const uint32_t v = (lvl[0] & 0xffu) | ((lvl[1] & 0xffu) << 8) |
+                           ((lvl[2] & 0xffu) << 16) | ((lvl[3] & 0xffu) << 24);
+        *reinterpret_cast<gp<uint32_t>>(glob(d.lmap) + 4ull * g) = v;
+    }
 }
 
 template <bool EMIT>
@@ -345,17 +396,19 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     const uint32_t g = lb * kBlock + threadIdx.x;
     const bool active = g < ngroups;
     uint32_t big = kNone;
-    const uint32_t cnt = active ? (uint32_t)walk_group<false>(d, g, nullptr, big) : 0u;
+    uint32_t lvl[4];
+    const uint32_t cnt = active ? (uint32_t)walk_group<false>(d, g, gp<uint32_t>(nullptr), big, lvl) : 0u;
     uint32_t total;
     const uint32_t excl = block_excl_scan(cnt, lds, total);
     if (!EMIT) {
-        if (threadIdx.x == 0) d.tcount[lb] = total;
+        if (threadIdx.x == 0) glob(d.tcount)[lb] = total;
         return;
     }
     if (active) {
-        const uint32_t base = d.tcount[lb] + excl;
-        walk_group<true>(d, g, d.leaves + base, big);
-        d.big_src[g] = big;
+        const uint32_t base = glob(d.tcount)[lb] + excl;
+        walk_group<true>(d, g, glob(d.leaves) + base, big, lvl);
+        glob(d.big_src)[g] = big;
+        write_level_map(d, g, lvl);
     }
 }
 
@@ -388,57 +441,115 @@ struct Cell {
     double z;
 };
 
+// Everything the FV1 update of one problem reads, as global pointers and
+// scalars; built once per problem (wave-uniform, so it lives in SGPRs).
 template <typename T>
-__device__ inline Cell<T> load_cell(const Desc& d, int cur, int n, uint32_t k)
+struct Fv1Ctx {
+    gp<const T> fin[3];    // current finest set
+    gp<T> fout[3];         // finest set being written
+    gp<const T> crs[3];    // coarse levels
+    gp<const double> zh;   // bed hierarchy
+    gp<const uint8_t> lmap;
+    gp<const uint32_t> leaves;
+    int L, Lg;
+    int bc[4];
+    double dx, dy, g, h_tol, manning_n, rain_rate;
+    double inlet_y0, inlet_y1, q_peak, t_peak, t_base;
+    double t, dt;
+    uint32_t nl;
+};
+
+template <typename T>
+__device__ inline void make_ctx(Fv1Ctx<T>& x, const Desc& d)
+{
+    const hw_scalars* sc = d.scal;
+    const int cur = uniform((int)sc->cur);
+    for (int v = 0; v < 3; ++v) {
+        x.fin[v] = glob(reinterpret_cast<const T*>(d.fine[cur][v]));
+        x.fout[v] = glob(reinterpret_cast<T*>(d.fine[cur ^ 1][v]));
+        x.crs[v] = glob(reinterpret_cast<const T*>(d.coarse[v]));
+    }
+    x.zh = glob(static_cast<const double*>(d.zhier));
+    x.lmap = glob(static_cast<const uint8_t*>(d.lmap));
+    x.leaves = glob(static_cast<const uint32_t*>(d.leaves));
+    x.L = d.L;
+    x.Lg = d.group_level;
+    for (int k = 0; k < 4; ++k) x.bc[k] = d.bc[k];
+    x.dx = d.dx;
+    x.dy = d.dy;
+    x.g = d.g;
+    x.h_tol = d.h_tol;
+    x.manning_n = d.manning_n;
+    x.rain_rate = d.rain_rate;
+    x.inlet_y0 = d.inlet_y0;
+    x.inlet_y1 = d.inlet_y1;
+    x.q_peak = d.q_peak;
+    x.t_peak = d.t_peak;
+    x.t_base = d.t_base;
+    x.t = sc->t;
+    x.dt = sc->dt;
+    x.nl = uniform((uint32_t)sc->n_leaves);
+}
+
+template <typename T>
+__device__ inline Cell<T> load_cell(const Fv1Ctx<T>& x, int n, uint32_t k)
 {
     Cell<T> c;
-    if (n == d.L) {
-        c.h = reinterpret_cast<const T*>(d.fine[cur][0])[k];
-        c.qx = reinterpret_cast<const T*>(d.fine[cur][1])[k];
-        c.qy = reinterpret_cast<const T*>(d.fine[cur][2])[k];
+    if (n == x.L) {
+        c.h = x.fin[0][k];
+        c.qx = x.fin[1][k];
+        c.qy = x.fin[2][k];
     } else {
         const uint64_t o = level_off(n) + k;
-        c.h = reinterpret_cast<const T*>(d.coarse[0])[o];
-        c.qx = reinterpret_cast<const T*>(d.coarse[1])[o];
-        c.qy = reinterpret_cast<const T*>(d.coarse[2])[o];
+        c.h = x.crs[0][o];
+        c.qx = x.crs[1][o];
+        c.qy = x.crs[2][o];
     }
-    c.z = d.zhier[level_off(n) + k];
+    c.z = x.zh[level_off(n) + k];
     return c;
 }
 
-// Neighbour of leaf (m, c) in direction dir (Fig. 3): the level-m cell on
-// that side if all its ancestors are significant, else the coarser leaf on
-// its path; a ghost copy of the leaf outside the domain.  Ancestors shared
-// with the leaf itself are significant, so the walk starts at the first
-// level where the two paths differ.
+// Same-level neighbour (Fig. 3) through the leaf-level map: the leaf that
+// contains the first finest descendant of the level-m cell cd is at level lv.
+// If lv >= m the level-m cell exists in the tree (it is that leaf or an
+// internal node) and its encoded values are used; otherwise the coarser leaf
+// at level lv contains it and is used.  Both follow the same root path, so
+// this is the first-insignificant-ancestor rule.  The level-m values are
+// loaded before lv is known (the slot always exists); only a coarser
+// neighbour costs a second load.
 template <typename T>
-__device__ inline Cell<T> neighbour(const Desc& d, int cur, int m, uint32_t c,
-                                    uint32_t i, uint32_t j, int dir,
-                                    const Cell<T>& own)
+__device__ inline Cell<T> neighbour_fix(const Fv1Ctx<T>& x, int m, uint32_t cd,
+                                        int lv, const Cell<T>& spec)
 {
-    const uint32_t S = 1u << m;
-    uint32_t ii = i, jj = j;
-    bool out = false;
-    if (dir == HW_W) { out = i == 0; ii = i - 1; }
-    if (dir == HW_E) { out = i + 1 >= S; ii = i + 1; }
-    if (dir == HW_S) { out = j == 0; jj = j - 1; }
-    if (dir == HW_N) { out = j + 1 >= S; jj = j + 1; }
-    if (out) {
-        Cell<T> g = own;
-        if (d.bc[dir] == HW_BC_WALL) {
-            if (dir == HW_W || dir == HW_E) g.qx = -g.qx;
-            else g.qy = -g.qy;
-        }
-        return g;
+    if (lv >= m) return spec;
+    return load_cell<T>(x, lv, cd >> (2 * (m - lv)));
+}
+
+template <typename T>
+__device__ inline Cell<T> ghost_cell(const Fv1Ctx<T>& x, int dir, const Cell<T>& own)
+{
+    Cell<T> g = own;
+    if (x.bc[dir] == HW_BC_WALL) {
+        if (dir == HW_W || dir == HW_E) g.qx = -g.qx;
+        else g.qy = -g.qy;
     }
-    const uint32_t cd = morton(ii, jj);
-    const uint32_t x = c ^ cd;
-    const int p = (31 - __clz(x)) >> 1;   // highest differing bit pair
-    for (int n = m - p; n < m; ++n) {
-        const uint32_t k = cd >> (2 * (m - n));
-        if (!d.sig[level_off(n) + k]) return load_cell<T>(d, cur, n, k);
+    return g;
+}
+
+template <typename T>
+__device__ inline void store_run(gp<T> p, uint32_t cnt, T v)
+{
+    if (cnt == 1) {
+        p[0] = v;
+        return;
     }
-    return load_cell<T>(d, cur, m, cd);
+    if (sizeof(T) == 8) {
+        const vd2 w = {(double)v, (double)v};
+        for (uint32_t q = 0; q < cnt; q += 2) *reinterpret_cast<gp<vd2>>(p + q) = w;
+    } else {
+        const vf4 w = {(float)v, (float)v, (float)v, (float)v};
+        for (uint32_t q = 0; q < cnt; q += 4) *reinterpret_cast<gp<vf4>>(p + q) = w;
+    }
 }
 
 template <typename T>
@@ -512,11 +623,12 @@ __device__ inline void face_flux(T hl, T unl, T utl, double zl, T hr, T unr,
     }
 }
 
-__device__ inline double inflow_rate(const Desc& d, double t)
+template <typename T>
+__device__ inline double inflow_rate(const Fv1Ctx<T>& x, double t)
 {
-    if (!(d.q_peak > 0.0)) return 0.0;
-    if (t <= d.t_peak) return d.q_peak * t / d.t_peak;
-    if (t <= d.t_base) return d.q_peak * (d.t_base - t) / (d.t_base - d.t_peak);
+    if (!(x.q_peak > 0.0)) return 0.0;
+    if (t <= x.t_peak) return x.q_peak * t / x.t_peak;
+    if (t <= x.t_base) return x.q_peak * (x.t_base - t) / (x.t_base - x.t_peak);
     return 0.0;
 }
 
@@ -591,23 +703,38 @@ __device__ inline void acc_flush(Acc& a, double (*red)[kPartial], double* rec)
 }
 
 template <typename T>
-__device__ inline void fv1_leaf(const Desc& d, int cur, double t, double dt,
-                                uint32_t idx, Acc& acc)
+__device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
 {
-    const int L = d.L;
+    const int L = x.L;
     const int m = level_of(idx);
     const uint32_t c = idx - (uint32_t)level_off(m);
     const uint32_t i = compact1by1(c), j = compact1by1(c >> 1);
-    const T g = (T)d.g;
-    const T tol = (T)d.h_tol;
-    const double dxm = ldexp(d.dx, L - m);
-    const double dym = ldexp(d.dy, L - m);
+    const T g = (T)x.g;
+    const T tol = (T)x.h_tol;
+    const double dt = x.dt;
+    const double dxm = ldexp(x.dx, L - m);
+    const double dym = ldexp(x.dy, L - m);
 
-    const Cell<T> own = load_cell<T>(d, cur, m, c);
-    const Cell<T> w = neighbour<T>(d, cur, m, c, i, j, HW_W, own);
-    const Cell<T> e = neighbour<T>(d, cur, m, c, i, j, HW_E, own);
-    const Cell<T> so = neighbour<T>(d, cur, m, c, i, j, HW_S, own);
-    const Cell<T> no = neighbour<T>(d, cur, m, c, i, j, HW_N, own);
+    const uint32_t S = 1u << m;
+    const int sh = 2 * (L - m);
+    const bool inW = i > 0, inE = i + 1 < S, inS = j > 0, inN = j + 1 < S;
+    const uint32_t cW = inW ? morton(i - 1, j) : c;
+    const uint32_t cE = inE ? morton(i + 1, j) : c;
+    const uint32_t cS = inS ? morton(i, j - 1) : c;
+    const uint32_t cN = inN ? morton(i, j + 1) : c;
+    const int lW = x.lmap[(uint64_t)cW << sh];
+    const int lE = x.lmap[(uint64_t)cE << sh];
+    const int lS = x.lmap[(uint64_t)cS << sh];
+    const int lN = x.lmap[(uint64_t)cN << sh];
+    const Cell<T> own = load_cell<T>(x, m, c);
+    const Cell<T> sW = load_cell<T>(x, m, cW);
+    const Cell<T> sE = load_cell<T>(x, m, cE);
+    const Cell<T> sS = load_cell<T>(x, m, cS);
+    const Cell<T> sN = load_cell<T>(x, m, cN);
+    const Cell<T> w = inW ? neighbour_fix<T>(x, m, cW, lW, sW) : ghost_cell<T>(x, HW_W, own);
+    const Cell<T> e = inE ? neighbour_fix<T>(x, m, cE, lE, sE) : ghost_cell<T>(x, HW_E, own);
+    const Cell<T> so = inS ? neighbour_fix<T>(x, m, cS, lS, sS) : ghost_cell<T>(x, HW_S, own);
+    const Cell<T> no = inN ? neighbour_fix<T>(x, m, cN, lN, sN) : ghost_cell<T>(x, HW_N, own);
 
     const T uc = velocity(own.h, own.qx, tol), vc = velocity(own.h, own.qy, tol);
     const T uw = velocity(w.h, w.qx, tol), vw = velocity(w.h, w.qy, tol);
@@ -637,16 +764,16 @@ __device__ inline void fv1_leaf(const Desc& d, int cur, double t, double dt,
     T qy = own.qy - rx * (FE[2] - FW[2]) - ry * ((GN[1] + PN) - (GS[1] + PS));
 
     // sources: rain, west-edge inflow, positivity, dry cells, friction
-    if (d.rain_rate != 0.0) h = h + (T)(dt * d.rain_rate);
-    if (i == 0 && d.q_peak > 0.0) {
+    if (x.rain_rate != 0.0) h = h + (T)(dt * x.rain_rate);
+    if (i == 0 && x.q_peak > 0.0) {
         const double y_lo = (double)j * dym;
-        const double lo = y_lo > d.inlet_y0 ? y_lo : d.inlet_y0;
+        const double lo = y_lo > x.inlet_y0 ? y_lo : x.inlet_y0;
         const double yhi = y_lo + dym;
-        const double hi = yhi < d.inlet_y1 ? yhi : d.inlet_y1;
+        const double hi = yhi < x.inlet_y1 ? yhi : x.inlet_y1;
         const double overlap = hi - lo;
         if (overlap > 0.0) {
-            const double width = d.inlet_y1 - d.inlet_y0;
-            const double q = inflow_rate(d, t);
+            const double width = x.inlet_y1 - x.inlet_y0;
+            const double q = inflow_rate(x, x.t);
             h = h + (T)(dt * q * overlap / (width * dxm * dym));
         }
     }
@@ -657,8 +784,8 @@ __device__ inline void fv1_leaf(const Desc& d, int cur, double t, double dt,
     if (h <= tol) {
         qx = T(0);
         qy = T(0);
-    } else if (d.manning_n > 0.0) {
-        const T nm = (T)d.manning_n;
+    } else if (x.manning_n > 0.0) {
+        const T nm = (T)x.manning_n;
         const T speed = sqrt(qx * qx + qy * qy) / h;
         const T cf = g * nm * nm / cbrt(h);
         const T den = T(1) + (T)dt * cf * speed / h;
@@ -669,17 +796,11 @@ __device__ inline void fv1_leaf(const Desc& d, int cur, double t, double dt,
     // write-back: every finest descendant of the leaf in the other set,
     // except for leaves coarser than a traversal group (k_fill copies
     // those from the first descendant)
-    const int sh = 2 * (L - m);
     const uint64_t f0 = (uint64_t)c << sh;
-    T* dh = reinterpret_cast<T*>(d.fine[cur ^ 1][0]);
-    T* dqx = reinterpret_cast<T*>(d.fine[cur ^ 1][1]);
-    T* dqy = reinterpret_cast<T*>(d.fine[cur ^ 1][2]);
-    const uint32_t cnt = m >= d.group_level ? (1u << sh) : 1u;
-    for (uint32_t q = 0; q < cnt; ++q) {
-        dh[f0 + q] = h;
-        dqx[f0 + q] = qx;
-        dqy[f0 + q] = qy;
-    }
+    const uint32_t cnt = m >= x.Lg ? (1u << sh) : 1u;
+    store_run<T>(x.fout[0] + f0, cnt, h);
+    store_run<T>(x.fout[1] + f0, cnt, qx);
+    store_run<T>(x.fout[2] + f0, cnt, qy);
 
     acc_max(acc, 0, wave_speed<T>(h, qx, qy, g, tol));
     acc_max(acc, 1, fabs((double)h));
@@ -695,8 +816,8 @@ __device__ inline void fv1_leaf(const Desc& d, int cur, double t, double dt,
 // is split into 8 contiguous segments, one per XCD (workgroups are dispatched
 // to XCDs round-robin), so that neighbouring leaves share an L2.  Each
 // workgroup leaves one partial record per problem.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fv1(const Desc* descs, int n)
+template <typename T, int MINW>
+__global__ __launch_bounds__(kBlock, MINW) void k_fv1(const Desc* descs, int n)
 {
     __shared__ uint32_t cpre[kMaxScen + 1];
     __shared__ double rec[kMaxScen][kPartial];
@@ -714,7 +835,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1(const Desc* descs, int n)
     }
     for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
     __syncthreads();
-    const uint32_t total = cpre[n];
+    const uint32_t total = uniform(cpre[n]);
     const uint32_t xcd = blockIdx.x & 7u;
     const uint32_t rank = blockIdx.x >> 3;
     const uint32_t g8 = gridDim.x >> 3;
@@ -725,24 +846,37 @@ __global__ __launch_bounds__(kBlock) void k_fv1(const Desc* descs, int n)
     Acc acc;
     acc_reset(acc);
     int cs = -1;
-    int cur = 0;
-    double t = 0.0, dt = 0.0;
-    uint32_t nl = 0;
+    Fv1Ctx<T> x;
+    uint32_t c0 = 0, c1 = 0;   // chunk range of the current problem
+    // the leaf index of the next chunk (same problem) is loaded one
+    // iteration ahead, so its latency overlaps the current leaf
+    uint32_t next_idx = 0;
+    bool next_ok = false;
     for (uint32_t ch = c_begin + rank; ch < c_end; ch += g8) {
-        int s = cs < 0 ? 0 : cs;
-        while (cpre[s + 1] <= ch) ++s;
-        if (s != cs) {
+        if (cs < 0 || ch >= c1) {
+            int s = cs < 0 ? 0 : cs;
+            while (cpre[s + 1] <= ch) ++s;
+            s = uniform(s);
             if (cs >= 0) acc_flush(acc, red, rec[cs]);
             cs = s;
-            const hw_scalars* sc = descs[s].scal;
-            cur = (int)sc->cur;
-            t = sc->t;
-            dt = sc->dt;
-            nl = (uint32_t)sc->n_leaves;
+            make_ctx<T>(x, descs[s]);
+            c0 = uniform(cpre[s]);
+            c1 = uniform(cpre[s + 1]);
+            next_ok = false;
         }
-        const Desc& d = descs[s];
-        const uint32_t leaf = (ch - cpre[s]) * kBlock + tid;
-        if (leaf < nl) fv1_leaf<T>(d, cur, t, dt, d.leaves[leaf], acc);
+        const uint32_t leaf = (ch - c0) * kBlock + tid;
+        uint32_t idx = 0;
+        if (leaf < x.nl) idx = next_ok ? next_idx : x.leaves[leaf];
+        const uint32_t nch = ch + g8;
+        next_ok = false;
+        if (nch < c_end && nch < c1) {
+            const uint32_t nleaf = (nch - c0) * kBlock + tid;
+            if (nleaf < x.nl) {
+                next_idx = x.leaves[nleaf];
+                next_ok = true;
+            }
+        }
+        if (leaf < x.nl) fv1_leaf<T>(x, idx, acc);
     }
     if (cs >= 0) acc_flush(acc, red, rec[cs]);
     for (int q = tid; q < n * kPartial; q += kBlock) {
@@ -764,16 +898,16 @@ __global__ __launch_bounds__(kBlock) void k_fill(Launch lc)
     if (sc->done) return;
     const uint32_t g = lb * kBlock + threadIdx.x;
     if (g >= (1u << (2 * d.group_level))) return;
-    const uint32_t src = d.big_src[g];
+    const uint32_t src = glob(d.big_src)[g];
     if (src == kNone) return;
     const int L = d.L;
     const int n = level_of(src);
     const uint64_t f0 = (uint64_t)(src - (uint32_t)level_off(n)) << (2 * (L - n));
     const int per = 1 << (2 * (L - d.group_level));
     const uint64_t base = (uint64_t)g * per;
-    const int o = sc->cur ^ 1;
+    const int o = uniform((int)sc->cur) ^ 1;
     for (int v = 0; v < 3; ++v) {
-        T* a = reinterpret_cast<T*>(d.fine[o][v]);
+        const gp<T> a = glob(reinterpret_cast<T*>(d.fine[o][v]));
         const T val = a[f0];
         for (int q = 0; q < per; ++q)
             if (base + q != f0) a[base + q] = val;
@@ -1018,13 +1152,23 @@ hipError_t launch_traverse(Launch lc, uint32_t nblocks, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
-                           hipStream_t s)
+template <typename T>
+static void launch_fv1_t(const Desc* descs, int n, uint32_t grid, int waves,
+                         hipStream_t s)
 {
-    if (prec == HW_FP64)
-        hipLaunchKernelGGL(k_fv1<double>, dim3(grid), dim3(kBlock), 0, s, descs, n);
-    else
-        hipLaunchKernelGGL(k_fv1<float>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+    switch (waves) {
+    case 5: hipLaunchKernelGGL((k_fv1<T, 5>), dim3(grid), dim3(kBlock), 0, s, descs, n); break;
+    case 6: hipLaunchKernelGGL((k_fv1<T, 6>), dim3(grid), dim3(kBlock), 0, s, descs, n); break;
+    case 8: hipLaunchKernelGGL((k_fv1<T, 8>), dim3(grid), dim3(kBlock), 0, s, descs, n); break;
+    default: hipLaunchKernelGGL((k_fv1<T, 1>), dim3(grid), dim3(kBlock), 0, s, descs, n); break;
+    }
+}
+
+hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
+                           int waves, hipStream_t s)
+{
+    if (prec == HW_FP64) launch_fv1_t<double>(descs, n, grid, waves, s);
+    else launch_fv1_t<float>(descs, n, grid, waves, s);
     return hipGetLastError();
 }
 
@@ -1046,7 +1190,7 @@ hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t 
 hipError_t launch_fv1(int prec, const Desc* descs, int n, uint32_t grid,
                       Launch fill, uint32_t fill_blocks, hipStream_t s)
 {
-    hipError_t e = launch_fv1_only(prec, descs, n, grid, s);
+    hipError_t e = launch_fv1_only(prec, descs, n, grid, 0, s);
     if (e == hipSuccess) e = launch_fill(prec, fill, fill_blocks, s);
     if (e == hipSuccess) e = launch_finalize(descs, n, grid, s);
     return e;
