@@ -78,9 +78,12 @@ def phase_bytes(L, w, hist):
 
 def time_single(hw, w, precision, steps, warmup, prof_steps):
     import torch
+    from paper_2206_05761_amd.autotune import autotune
     log(f"[bench] {w.name} {precision}: ingest")
     sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision=precision)
-    plan = hw.Plan([sim.problem], [sim.buffers])
+    best, table = autotune([sim.problem], [sim.buffers], use_cache=False)
+    log(f"[bench] {precision}: autotuned {best}")
+    plan = hw.Plan([sim.problem], [sim.buffers], tuning=best)
     hw.hwfv1_run(sim.problem, sim.buffers, warmup, plan=plan, stats=True)
     s0 = sim.scalars()
     torch.cuda.synchronize()
@@ -102,7 +105,7 @@ def time_single(hw, w, precision, steps, warmup, prof_steps):
     res = dict(sim=sim, plan=plan, ms=ms, wall=wall, steps=steps,
                leaf_updates=int(s1["leaf_updates"] - s0["leaf_updates"]),
                prof={k: v / prof_steps for k, v in prof.items()}, hist=hist,
-               scalars=s2)
+               scalars=s2, tuning=best, tuning_table=table)
     return res
 
 
@@ -159,7 +162,11 @@ def bench_batch(hw, steps, warmup, n_members):
     sims = [hw.Simulation(m.params, m.h, m.qx, m.qy, m.z, precision="fp32_bulk")
             for m in members]
     cells = sum(4 ** m.L for m in members)
-    plan = hw.Plan([s.problem for s in sims], [s.buffers for s in sims])
+    from paper_2206_05761_amd.autotune import autotune
+    best, table = autotune([s.problem for s in sims], [s.buffers for s in sims],
+                           use_cache=False)
+    log(f"[bench] batch: autotuned {best}")
+    plan = hw.Plan([s.problem for s in sims], [s.buffers for s in sims], tuning=best)
     hw.hwfv1_run_batch(plan, warmup, stats=True)
     lu0 = sum(s.scalars()["leaf_updates"] for s in sims)
     torch.cuda.synchronize()
@@ -181,6 +188,7 @@ def bench_batch(hw, steps, warmup, n_members):
         "ms_per_step": round(ms / steps, 4), "dtype": "f32 (FP64 significance)",
         "levels": {str(L): levels.count(L) for L in sorted(set(levels))},
         "phase_ms": {k: round(v / 5, 4) for k, v in prof.items()},
+        "tuning": best, "autotune_ms_per_step": table,
     }
     plan.close()
     for s in sims:
@@ -258,6 +266,7 @@ def main():
         "leaf_updates_per_s": r64["leaf_updates"] / (r64["ms"] * 1e-3),
         "n_leaves": int(r64["scalars"]["n_leaves"]),
         "roofline": roofline(r64, L, 8),
+        "tuning": r64["tuning"], "autotune_ms_per_step": r64["tuning_table"],
     }
     if not args.no_fp32:
         r32 = time_single(hw, w, "fp32_bulk", args.steps, args.warmup, args.prof_steps)
@@ -266,6 +275,7 @@ def main():
             "ms_per_step": round(r32["ms"] / args.steps, 5),
             "leaf_updates_per_s": r32["leaf_updates"] / (r32["ms"] * 1e-3),
             "roofline": roofline(r32, L, 4),
+            "tuning": r32["tuning"],
             "error_vs_fp64": fp32_error(hw, r64, r32),
         }
         r32["plan"].close()

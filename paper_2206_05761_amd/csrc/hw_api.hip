@@ -78,6 +78,12 @@ uint32_t n_coarse_blocks(int L)
 {
     return (uint32_t)((hw::level_off(L) + hw::kBlock - 1) / hw::kBlock);
 }
+// regularisation threads: one per 2x2 block of levels 1..L-1 (at least one)
+uint32_t n_reg_blocks(int L)
+{
+    const uint64_t t = L >= 2 ? hw::level_off(L - 1) : 1;
+    return (uint32_t)((t + hw::kBlock - 1) / hw::kBlock);
+}
 
 // Levels per encoding pass for a given number of in-register levels.
 int pass_levels(int cp) { return cp + 4; }
@@ -91,7 +97,7 @@ uint32_t encode_blocks(int L, int pass, int tl)
 }
 
 struct WorkLayout {
-    size_t desc, tcount, big_src, lmap, partials, total;
+    size_t desc, tcount, big_src, gcode, lmap, partials, total;
 };
 
 WorkLayout work_layout(int L)
@@ -104,6 +110,8 @@ WorkLayout work_layout(int L)
     o = align_up(o + (n_trav(L) + 1) * sizeof(uint32_t));
     w.big_src = o;
     o = align_up(o + n_groups(L) * sizeof(uint32_t));
+    w.gcode = o;
+    o = align_up(o + n_groups(L));
     w.lmap = o;
     o = align_up(o + (size_t)hw_n_fine_(L));
     w.partials = o;
@@ -213,6 +221,7 @@ Desc make_desc(const hw_problem* p, const hw_buffers* b, double* partials)
     d.tcount = reinterpret_cast<uint32_t*>(wk + w.tcount);
     d.big_src = reinterpret_cast<uint32_t*>(wk + w.big_src);
     d.lmap = reinterpret_cast<uint8_t*>(wk + w.lmap);
+    d.gcode = reinterpret_cast<uint8_t*>(wk + w.gcode);
     d.partials = partials ? partials : reinterpret_cast<double*>(wk + w.partials);
     d.ntrav = n_trav(p->L);
     return d;
@@ -278,8 +287,9 @@ struct hw_plan {
     int passes = 0;
     std::vector<uint32_t> enc_blocks;         // per pass
     std::vector<const uint32_t*> enc_prefix;  // per pass (device)
-    uint32_t coarse_blocks = 0, trav_blocks = 0;
+    uint32_t coarse_blocks = 0, trav_blocks = 0, reg_blocks = 0;
     const uint32_t* coarse_prefix = nullptr;
+    const uint32_t* reg_prefix = nullptr;
     const uint32_t* trav_prefix = nullptr;
     // captured step
     hipGraph_t graph = nullptr;
@@ -304,8 +314,8 @@ hipError_t enqueue_phase(hw_plan* pl, int phase, hipStream_t s)
         }
         break;
     case HW_PH_REGULARISE:
-        e = hw::launch_regularise(Launch{pl->d_desc, pl->coarse_prefix, n},
-                                  pl->coarse_blocks, s);
+        e = hw::launch_regularise(Launch{pl->d_desc, pl->reg_prefix, n},
+                                  pl->reg_blocks, s);
         break;
     case HW_PH_TRAVERSE:
         e = hw::launch_traverse(Launch{pl->d_desc, pl->trav_prefix, n}, pl->trav_blocks, s);
@@ -514,7 +524,7 @@ int mra_flag(const hw_problem* p, const hw_buffers* b, hipStream_t stream)
     hipError_t e = hw::launch_flag_only(p->precision, Launch{dd, nullptr, 1},
                                         n_coarse_blocks(p->L), stream);
     if (e == hipSuccess)
-        e = hw::launch_regularise(Launch{dd, nullptr, 1}, n_coarse_blocks(p->L), stream);
+        e = hw::launch_regularise(Launch{dd, nullptr, 1}, n_reg_blocks(p->L), stream);
     if (e != hipSuccess) return hip_fail(e, "flag launch");
     return ok();
 }
@@ -642,6 +652,16 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
         pre.push_back(acc);
         pl->coarse_blocks = acc;
     }
+    const size_t reg_off = pre.size();
+    {
+        uint32_t acc = 0;
+        for (int i = 0; i < n; ++i) {
+            pre.push_back(acc);
+            acc += n_reg_blocks(problems[i].L);
+        }
+        pre.push_back(acc);
+        pl->reg_blocks = acc;
+    }
     const size_t trav_off = pre.size();
     {
         uint32_t acc = 0;
@@ -671,6 +691,7 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
     for (int k = 0; k < pl->passes; ++k)
         pl->enc_prefix.push_back(single ? nullptr : d_pre + enc_off[k]);
     pl->coarse_prefix = single ? nullptr : d_pre + coarse_off;
+    pl->reg_prefix = single ? nullptr : d_pre + reg_off;
     pl->trav_prefix = single ? nullptr : d_pre + trav_off;
     e = hipMemcpy(pl->d_desc, pl->host_desc.data(), n * sizeof(Desc), hipMemcpyHostToDevice);
     if (e == hipSuccess)

@@ -34,6 +34,7 @@ struct Desc {
     uint32_t* tcount;      // traversal workgroup counts / offsets
     uint32_t* big_src;     // per group: leaf index of a coarser leaf or kNone
     uint8_t* lmap;         // per finest cell: level of the leaf containing it
+    uint8_t* gcode;        // per traversal group: walk summary (count pass)
     double* partials;      // FV1 / ingest partial records, kPartial each
     uint32_t ntrav;        // traversal workgroups of this problem
     uint32_t pad1;
@@ -77,6 +78,29 @@ __host__ __device__ inline uint32_t morton(uint32_t i, uint32_t j)
 {
     return part1by1(i) | (part1by1(j) << 1);
 }
+
+// Morton neighbours on a level whose codes use the bits in
+// xm (column bits) and ym = xm << 1 (row bits): increment or decrement one
+// coordinate and carry through its own bits only.
+__host__ __device__ inline uint32_t morton_xp(uint32_t c, uint32_t xm, uint32_t ym)
+{
+    return (((c | ym) + 1u) & xm) | (c & ym);
+}
+__host__ __device__ inline uint32_t morton_xm(uint32_t c, uint32_t xm, uint32_t ym)
+{
+    return (((c & xm) - 1u) & xm) | (c & ym);
+}
+__host__ __device__ inline uint32_t morton_yp(uint32_t c, uint32_t xm, uint32_t ym)
+{
+    return (((c | xm) + 1u) & ym) | (c & xm);
+}
+__host__ __device__ inline uint32_t morton_ym(uint32_t c, uint32_t xm, uint32_t ym)
+{
+    return (((c & ym) - 1u) & ym) | (c & xm);
+}
+
+// True on every lane if the condition holds on at least one lane of the wave.
+__device__ inline bool wave_any(bool b) { return __ballot(b) != 0; }
 
 // Level of a hierarchy Z-order index: the n with (4^n-1)/3 <= idx <
 // (4^(n+1)-1)/3, i.e. floor(log4(3 idx + 1)).

@@ -273,19 +273,50 @@ __global__ __launch_bounds__(kBlock) void k_regularise(Launch lc)
     const int s = scen_of(lc, blockIdx.x, b);
     const Desc& d = lc.descs[s];
     if (d.scal->done) return;
-    const uint64_t c = (uint64_t)b * kBlock + threadIdx.x;
-    if (c >= level_off(d.L)) return;
-    const int n = level_of((uint32_t)c);
-    const uint32_t k = (uint32_t)(c - level_off(n));
-    const uint32_t i = compact1by1(k), j = compact1by1(k >> 1);
-    const uint32_t S = 1u << n;
-    const gp<const uint8_t> raw = glob(static_cast<const uint8_t*>(d.raw)) + level_off(n);
-    uint8_t f = raw[k];
-    if (i > 0) f |= raw[morton(i - 1, j)];
-    if (i + 1 < S) f |= raw[morton(i + 1, j)];
-    if (j > 0) f |= raw[morton(i, j - 1)];
-    if (j + 1 < S) f |= raw[morton(i, j + 1)];
-    glob(d.sig)[c] = f ? 1 : 0;
+    const int L = d.L;
+    const gp<const uint8_t> raw = glob(static_cast<const uint8_t*>(d.raw));
+    const gp<uint8_t> sig = glob(d.sig);
+    // One thread per 2x2 Morton block of cells on levels 1..L-1; block t
+    // of the whole index space [0, (4^(L-1)-1)/3) sits on level
+    // n = level_of(t) + 1 with block code q.  Thread 0 also does level 0,
+    // which has no neighbours.
+    const uint32_t t = b * kBlock + threadIdx.x;
+    if (t == 0) sig[0] = raw[0] ? 1 : 0;
+    if (L < 2 || t >= (uint32_t)level_off(L - 1)) return;
+    const int n = level_of(t) + 1;
+    const uint32_t q = t - (uint32_t)level_off(n - 1);
+    // blocks live on level n-1: codes use 2(n-1) bits
+    const uint32_t bm = n > 1 ? (0xffffffffu >> (32 - 2 * (n - 1))) : 0u;
+    const uint32_t xm = 0x55555555u & bm, ym = 0xaaaaaaaau & bm;
+    const uint64_t base = level_off(n);
+    const uint64_t o = base + 4ull * q;
+    const uint8_t r0 = raw[o], r1 = raw[o + 1], r2 = raw[o + 2], r3 = raw[o + 3];
+    uint8_t w1 = 0, w3 = 0, e0 = 0, e2 = 0, s2 = 0, s3 = 0, n0 = 0, n1 = 0;
+    if ((q & xm) != 0) {
+        const uint64_t ow = base + 4ull * morton_xm(q, xm, ym);
+        w1 = raw[ow + 1];
+        w3 = raw[ow + 3];
+    }
+    if ((q & xm) != xm) {
+        const uint64_t oe = base + 4ull * morton_xp(q, xm, ym);
+        e0 = raw[oe];
+        e2 = raw[oe + 2];
+    }
+    if ((q & ym) != 0) {
+        const uint64_t os = base + 4ull * morton_ym(q, xm, ym);
+        s2 = raw[os + 2];
+        s3 = raw[os + 3];
+    }
+    if ((q & ym) != ym) {
+        const uint64_t on = base + 4ull * morton_yp(q, xm, ym);
+        n0 = raw[on];
+        n1 = raw[on + 1];
+    }
+    // children 0 (SW), 1 (SE), 2 (NW), 3 (NE) of the block
+    sig[o] = (r0 | r1 | r2 | w1 | s2) ? 1 : 0;
+    sig[o + 1] = (r1 | r0 | r3 | e0 | s3) ? 1 : 0;
+    sig[o + 2] = (r2 | r3 | r0 | w3 | n0) ? 1 : 0;
+    sig[o + 3] = (r3 | r2 | r1 | e2 | n1) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -299,9 +330,11 @@ __global__ __launch_bounds__(kBlock) void k_regularise(Launch lc)
 // records the leaf for the copy-down; otherwise it expands the at most two
 // levels below g.  Leaves come out in ascending first-descendant order.
 
-template <bool WRITE>
-__device__ inline int walk_group(const Desc& d, uint32_t g, gp<uint32_t> out,
-                                 uint32_t& big, uint32_t lvl[4])
+// Walk of group g from the root (Algorithm 5 for its 4^(L-Lg) finest
+// cells), summarised in one byte: the level (< 15) where the path meets an
+// insignificant cell, or 15 when g is significant, with the significance of
+// g's four children in the high nibble.
+__device__ inline uint32_t walk_code(const Desc& d, uint32_t g)
 {
     const int L = d.L;
     const int Lg = d.group_level;
@@ -316,25 +349,40 @@ __device__ inline int walk_group(const Desc& d, uint32_t g, gp<uint32_t> out,
         pf[n] = sig[level_off(nn) + (g >> (2 * (Lg - nn)))];
     }
     const int n1 = Lg + 1;
-    const int nk = n1 < L ? n1 : Lg;      // in-bounds stand-in when n1 == L
     const uint64_t kb = n1 < L ? level_off(n1) + 4ull * g : level_off(Lg) + g;
     uint8_t kf[4];
 #pragma unroll
     for (int c1 = 0; c1 < 4; ++c1) kf[c1] = sig[n1 < L ? kb + c1 : kb];
-    (void)nk;
     uint32_t path = 0;
 #pragma unroll
     for (int n = 0; n < HW_MAX_L; ++n)
         if (n <= Lg && pf[n]) path |= 1u << n;
+    const int n = __ffs(~path) - 1;   // first insignificant level on the path
+    if (n <= Lg) return (uint32_t)n;
     uint32_t kids = 0;
     if (n1 < L) {
 #pragma unroll
         for (int c1 = 0; c1 < 4; ++c1)
             if (kf[c1]) kids |= 1u << c1;
     }
+    return 15u | (kids << 4);
+}
+
+// Leaves of group g from its walk code, in ascending first-descendant
+// order.  A leaf coarser than the group is listed only by the group that
+// holds its first finest descendant (so each leaf appears once) and is
+// recorded in big for the copy-down; lvl receives the leaf level of each
+// quarter of the group.
+template <bool WRITE>
+__device__ inline int group_leaves(const Desc& d, uint32_t g, uint32_t code,
+                                   gp<uint32_t> out, uint32_t& big,
+                                   uint32_t lvl[4])
+{
+    const int Lg = d.group_level;
+    const int n1 = Lg + 1;
     int cnt = 0;
     big = kNone;
-    const int n = __ffs(~path) - 1;   // first insignificant level on the path
+    const int n = (int)(code & 15u);
     if (n < Lg) {
         const uint32_t k = g >> (2 * (Lg - n));
         const uint32_t idx = (uint32_t)level_off(n) + k;
@@ -351,6 +399,7 @@ __device__ inline int walk_group(const Desc& d, uint32_t g, gp<uint32_t> out,
         lvl[0] = lvl[1] = lvl[2] = lvl[3] = (uint32_t)Lg;
         return cnt + 1;
     }
+    const uint32_t kids = code >> 4;
     for (uint32_t c1 = 0; c1 < 4; ++c1) {
         const uint32_t k1 = 4 * g + c1;
         if (!((kids >> c1) & 1u)) {
@@ -384,6 +433,10 @@ __device__ inline void write_level_map(const Desc& d, uint32_t g, const uint32_t
     }
 }
 
+// Count pass (EMIT = false): walk, store the walk code of each group and
+// the workgroup's leaf count.  Emit pass: rebuild the leaves from the codes,
+// place them at the workgroup offset plus the in-workgroup prefix, and write
+// the copy-down table and the leaf-level map.
 template <bool EMIT>
 __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
 {
@@ -395,9 +448,20 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     const uint32_t ngroups = 1u << (2 * d.group_level);
     const uint32_t g = lb * kBlock + threadIdx.x;
     const bool active = g < ngroups;
+    const gp<uint8_t> codes = glob(d.gcode);
+    uint32_t code = 0;
+    if (active) {
+        if (EMIT) {
+            code = codes[g];
+        } else {
+            code = walk_code(d, g);
+            codes[g] = (uint8_t)code;
+        }
+    }
     uint32_t big = kNone;
     uint32_t lvl[4];
-    const uint32_t cnt = active ? (uint32_t)walk_group<false>(d, g, gp<uint32_t>(nullptr), big, lvl) : 0u;
+    const uint32_t cnt =
+        active ? (uint32_t)group_leaves<false>(d, g, code, gp<uint32_t>(nullptr), big, lvl) : 0u;
     uint32_t total;
     const uint32_t excl = block_excl_scan(cnt, lds, total);
     if (!EMIT) {
@@ -406,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     }
     if (active) {
         const uint32_t base = glob(d.tcount)[lb] + excl;
-        walk_group<true>(d, g, glob(d.leaves) + base, big, lvl);
+        group_leaves<true>(d, g, code, glob(d.leaves) + base, big, lvl);
         glob(d.big_src)[g] = big;
         write_level_map(d, g, lvl);
     }
@@ -457,7 +521,19 @@ struct Fv1Ctx {
     double inlet_y0, inlet_y1, q_peak, t_peak, t_base;
     double t, dt;
     uint32_t nl;
+    const double* rxy;     // LDS: dt/dx_m at [2m], dt/dy_m at [2m+1]
 };
+
+// dt / (cell size of level m) for every level, the same divisions the
+// update performs, done once per problem by one thread into LDS.
+__device__ inline void fill_rxy(double* rxy, const Desc& d, double dt)
+{
+    if (threadIdx.x == 0)
+        for (int m = 0; m <= d.L; ++m) {
+            rxy[2 * m] = dt / ldexp(d.dx, d.L - m);
+            rxy[2 * m + 1] = dt / ldexp(d.dy, d.L - m);
+        }
+}
 
 template <typename T>
 __device__ inline void make_ctx(Fv1Ctx<T>& x, const Desc& d)
@@ -507,6 +583,27 @@ __device__ inline Cell<T> load_cell(const Fv1Ctx<T>& x, int n, uint32_t k)
     }
     c.z = x.zh[level_off(n) + k];
     return c;
+}
+
+template <typename T>
+__device__ inline T load_h(const Fv1Ctx<T>& x, int n, uint32_t k)
+{
+    return n == x.L ? x.fin[0][k] : x.crs[0][level_off(n) + k];
+}
+
+// discharges and bed of the cell (n, k); h is already in c
+template <typename T>
+__device__ inline void load_rest(const Fv1Ctx<T>& x, int n, uint32_t k, Cell<T>& c)
+{
+    if (n == x.L) {
+        c.qx = x.fin[1][k];
+        c.qy = x.fin[2][k];
+    } else {
+        const uint64_t o = level_off(n) + k;
+        c.qx = x.crs[1][o];
+        c.qy = x.crs[2][o];
+    }
+    c.z = x.zh[level_off(n) + k];
 }
 
 // Same-level neighbour (Fig. 3) through the leaf-level map: the leaf that
@@ -708,39 +805,99 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
     const int L = x.L;
     const int m = level_of(idx);
     const uint32_t c = idx - (uint32_t)level_off(m);
-    const uint32_t i = compact1by1(c), j = compact1by1(c >> 1);
     const T g = (T)x.g;
     const T tol = (T)x.h_tol;
     const double dt = x.dt;
     const double dxm = ldexp(x.dx, L - m);
     const double dym = ldexp(x.dy, L - m);
 
-    const uint32_t S = 1u << m;
+    const uint32_t lvmask = m > 0 ? (0xffffffffu >> (32 - 2 * m)) : 0u;
+    const uint32_t xm = 0x55555555u & lvmask, ym = 0xaaaaaaaau & lvmask;
     const int sh = 2 * (L - m);
-    const bool inW = i > 0, inE = i + 1 < S, inS = j > 0, inN = j + 1 < S;
-    const uint32_t cW = inW ? morton(i - 1, j) : c;
-    const uint32_t cE = inE ? morton(i + 1, j) : c;
-    const uint32_t cS = inS ? morton(i, j - 1) : c;
-    const uint32_t cN = inN ? morton(i, j + 1) : c;
+    const bool inW = (c & xm) != 0, inE = (c & xm) != xm;
+    const bool inS = (c & ym) != 0, inN = (c & ym) != ym;
+    const uint32_t cW = inW ? morton_xm(c, xm, ym) : c;
+    const uint32_t cE = inE ? morton_xp(c, xm, ym) : c;
+    const uint32_t cS = inS ? morton_ym(c, xm, ym) : c;
+    const uint32_t cN = inN ? morton_yp(c, xm, ym) : c;
     const int lW = x.lmap[(uint64_t)cW << sh];
     const int lE = x.lmap[(uint64_t)cE << sh];
     const int lS = x.lmap[(uint64_t)cS << sh];
     const int lN = x.lmap[(uint64_t)cN << sh];
-    const Cell<T> own = load_cell<T>(x, m, c);
-    const Cell<T> sW = load_cell<T>(x, m, cW);
-    const Cell<T> sE = load_cell<T>(x, m, cE);
-    const Cell<T> sS = load_cell<T>(x, m, cS);
-    const Cell<T> sN = load_cell<T>(x, m, cN);
-    const Cell<T> w = inW ? neighbour_fix<T>(x, m, cW, lW, sW) : ghost_cell<T>(x, HW_W, own);
-    const Cell<T> e = inE ? neighbour_fix<T>(x, m, cE, lE, sE) : ghost_cell<T>(x, HW_E, own);
-    const Cell<T> so = inS ? neighbour_fix<T>(x, m, cS, lS, sS) : ghost_cell<T>(x, HW_S, own);
-    const Cell<T> no = inN ? neighbour_fix<T>(x, m, cN, lN, sN) : ghost_cell<T>(x, HW_N, own);
+    // Phase 1: depths only.  The level-m neighbour depth is loaded before its
+    // level is known (the slot always exists); a coarser neighbour (lv < m)
+    // is re-read from its leaf.
+    const T h_own = load_h<T>(x, m, c);
+    T hW = load_h<T>(x, m, cW), hE = load_h<T>(x, m, cE);
+    T hS = load_h<T>(x, m, cS), hN = load_h<T>(x, m, cN);
+    const int nW = lW < m ? lW : m, nE = lE < m ? lE : m;
+    const int nS = lS < m ? lS : m, nN = lN < m ? lN : m;
+    const uint32_t kW = cW >> (2 * (m - nW)), kE = cE >> (2 * (m - nE));
+    const uint32_t kS = cS >> (2 * (m - nS)), kN = cN >> (2 * (m - nN));
+    if (nW < m) hW = load_h<T>(x, nW, kW);
+    if (nE < m) hE = load_h<T>(x, nE, kE);
+    if (nS < m) hS = load_h<T>(x, nS, kS);
+    if (nN < m) hN = load_h<T>(x, nN, kN);
+    if (!inW) hW = h_own;
+    if (!inE) hE = h_own;
+    if (!inS) hS = h_own;
+    if (!inN) hN = h_own;
 
-    const T uc = velocity(own.h, own.qx, tol), vc = velocity(own.h, own.qy, tol);
-    const T uw = velocity(w.h, w.qx, tol), vw = velocity(w.h, w.qy, tol);
-    const T ue = velocity(e.h, e.qx, tol), ve = velocity(e.h, e.qy, tol);
-    const T us = velocity(so.h, so.qx, tol), vs = velocity(so.h, so.qy, tol);
-    const T un = velocity(no.h, no.qx, tol), vn = velocity(no.h, no.qy, tol);
+    // Exact dry shortcut: with the cell and its four neighbours dry every
+    // face flux is zero, so h - rx*(0-0) - ry*(0-0) = h; with no rain and no
+    // inflow on the cell the depth stays <= h_tol and the discharges are
+    // reset to zero.  Taken only when it holds on the whole wave.
+    bool inflow_here = false;
+    if (!inW && x.q_peak > 0.0) {
+        const double y_lo = (double)compact1by1(c >> 1) * dym;
+        const double lo = y_lo > x.inlet_y0 ? y_lo : x.inlet_y0;
+        const double yhi = y_lo + dym;
+        const double hi = yhi < x.inlet_y1 ? yhi : x.inlet_y1;
+        inflow_here = hi - lo > 0.0 && inflow_rate(x, x.t) != 0.0;
+    }
+    const bool dry5 = h_own <= tol && hW <= tol && hE <= tol && hS <= tol && hN <= tol;
+    const int sh2 = sh;
+    const uint64_t f0 = (uint64_t)c << sh2;
+    const uint32_t cnt = m >= x.Lg ? (1u << sh2) : 1u;
+    if (!wave_any(!(dry5 && !inflow_here)) && x.rain_rate == 0.0) {
+        store_run<T>(x.fout[0] + f0, cnt, h_own);
+        store_run<T>(x.fout[1] + f0, cnt, T(0));
+        store_run<T>(x.fout[2] + f0, cnt, T(0));
+        acc_max(acc, 1, fabs((double)h_own));
+        acc.v[4] += ((double)h_own * dxm) * dym;
+        return;
+    }
+
+    // Phase 2: discharges and beds of the five states.
+    Cell<T> own, w, e, so, no;
+    own.h = h_own;
+    load_rest<T>(x, m, c, own);
+    w.h = hW;
+    e.h = hE;
+    so.h = hS;
+    no.h = hN;
+    if (inW) load_rest<T>(x, nW, kW, w); else w = ghost_cell<T>(x, HW_W, own);
+    if (inE) load_rest<T>(x, nE, kE, e); else e = ghost_cell<T>(x, HW_E, own);
+    if (inS) load_rest<T>(x, nS, kS, so); else so = ghost_cell<T>(x, HW_S, own);
+    if (inN) load_rest<T>(x, nN, kN, no); else no = ghost_cell<T>(x, HW_N, own);
+
+    // Velocities only matter on faces with a wet side; a wave whose five
+    // states are all dry skips the divisions (values stay 0 and unused).
+    T uc = T(0), vc = T(0), uw = T(0), vw = T(0), ue = T(0), ve = T(0);
+    T us = T(0), vs = T(0), un = T(0), vn = T(0);
+    const bool wet = own.h > tol || w.h > tol || e.h > tol || so.h > tol || no.h > tol;
+    if (wave_any(wet)) {
+        uc = velocity(own.h, own.qx, tol);
+        vc = velocity(own.h, own.qy, tol);
+        uw = velocity(w.h, w.qx, tol);
+        vw = velocity(w.h, w.qy, tol);
+        ue = velocity(e.h, e.qx, tol);
+        ve = velocity(e.h, e.qy, tol);
+        us = velocity(so.h, so.qx, tol);
+        vs = velocity(so.h, so.qy, tol);
+        un = velocity(no.h, no.qx, tol);
+        vn = velocity(no.h, no.qy, tol);
+    }
 
     T FE[3], FW[3], GN[3], GS[3];
     T hcE, hcW, hcN, hcS, unused;
@@ -757,16 +914,16 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
     const T PW = hg * (h2 - hcW * hcW);
     const T PN = hg * (h2 - hcN * hcN);
     const T PS = hg * (h2 - hcS * hcS);
-    const T rx = (T)(dt / dxm);
-    const T ry = (T)(dt / dym);
+    const T rx = (T)x.rxy[2 * m];
+    const T ry = (T)x.rxy[2 * m + 1];
     T h = own.h - rx * (FE[0] - FW[0]) - ry * (GN[0] - GS[0]);
     T qx = own.qx - rx * ((FE[1] + PE) - (FW[1] + PW)) - ry * (GN[2] - GS[2]);
     T qy = own.qy - rx * (FE[2] - FW[2]) - ry * ((GN[1] + PN) - (GS[1] + PS));
 
     // sources: rain, west-edge inflow, positivity, dry cells, friction
     if (x.rain_rate != 0.0) h = h + (T)(dt * x.rain_rate);
-    if (i == 0 && x.q_peak > 0.0) {
-        const double y_lo = (double)j * dym;
+    if (!inW && x.q_peak > 0.0) {
+        const double y_lo = (double)compact1by1(c >> 1) * dym;
         const double lo = y_lo > x.inlet_y0 ? y_lo : x.inlet_y0;
         const double yhi = y_lo + dym;
         const double hi = yhi < x.inlet_y1 ? yhi : x.inlet_y1;
@@ -796,8 +953,6 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
     // write-back: every finest descendant of the leaf in the other set,
     // except for leaves coarser than a traversal group (k_fill copies
     // those from the first descendant)
-    const uint64_t f0 = (uint64_t)c << sh;
-    const uint32_t cnt = m >= x.Lg ? (1u << sh) : 1u;
     store_run<T>(x.fout[0] + f0, cnt, h);
     store_run<T>(x.fout[1] + f0, cnt, qx);
     store_run<T>(x.fout[2] + f0, cnt, qy);
@@ -822,6 +977,7 @@ __global__ __launch_bounds__(kBlock, MINW) void k_fv1(const Desc* descs, int n)
     __shared__ uint32_t cpre[kMaxScen + 1];
     __shared__ double rec[kMaxScen][kPartial];
     __shared__ double red[kBlock / kWave][kPartial];
+    __shared__ double rxy[2 * (HW_MAX_L + 1)];
     const int tid = threadIdx.x;
     if (tid == 0) {
         uint32_t a = 0;
@@ -857,9 +1013,12 @@ __global__ __launch_bounds__(kBlock, MINW) void k_fv1(const Desc* descs, int n)
             int s = cs < 0 ? 0 : cs;
             while (cpre[s + 1] <= ch) ++s;
             s = uniform(s);
-            if (cs >= 0) acc_flush(acc, red, rec[cs]);
+            if (cs >= 0) acc_flush(acc, red, rec[cs]);   // ends with a barrier
             cs = s;
             make_ctx<T>(x, descs[s]);
+            fill_rxy(rxy, descs[s], x.dt);
+            __syncthreads();
+            x.rxy = rxy;
             c0 = uniform(cpre[s]);
             c1 = uniform(cpre[s + 1]);
             next_ok = false;

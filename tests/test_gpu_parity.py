@@ -291,3 +291,18 @@ def test_launch_shapes_do_not_change_results(hw, precision):
             for x, y in zip(ref, out):
                 assert np.array_equal(x, y)
         plan.close()
+
+
+def test_autotune_restores_state_and_picks_a_candidate(hw):
+    from paper_2206_05761_amd.autotune import CANDIDATES, autotune
+    w = W.circular_dambreak_l10(L=8)
+    sim = _sim(hw, w)
+    sim.run(5)
+    before = sim.export() + (sim.scalars()["t"], sim.scalars()["step"])
+    best, table = autotune([sim.problem], [sim.buffers], steps=3, warmup=1,
+                           cache_path=None)
+    after = sim.export() + (sim.scalars()["t"], sim.scalars()["step"])
+    assert best in CANDIDATES and len(table) == len(CANDIDATES)
+    for x, y in zip(before[:3], after[:3]):
+        assert np.array_equal(x, y)
+    assert before[3:] == after[3:]
