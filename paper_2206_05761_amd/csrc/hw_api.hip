@@ -97,7 +97,7 @@ uint32_t encode_blocks(int L, int pass, int tl)
 }
 
 struct WorkLayout {
-    size_t desc, tcount, big_src, gcode, lmap, partials, total;
+    size_t desc, tcount, big_src, gcode, lmap, wet, partials, total;
 };
 
 WorkLayout work_layout(int L)
@@ -114,8 +114,10 @@ WorkLayout work_layout(int L)
     o = align_up(o + n_groups(L));
     w.lmap = o;
     o = align_up(o + (size_t)hw_n_fine_(L));
+    w.wet = o;
+    o = align_up(o + 4 * ((size_t)hw_n_fine_(L) / (hw::kLeafBatch * hw::kBlock) + 1));
     w.partials = o;
-    o = align_up(o + (size_t)hw::kMaxFv1Grid * hw::kPartial * sizeof(double));
+    o = align_up(o + 2 * (size_t)hw::kMaxFv1Grid * hw::kPartial * sizeof(double));
     w.total = o;
     return w;
 }
@@ -222,6 +224,7 @@ Desc make_desc(const hw_problem* p, const hw_buffers* b, double* partials)
     d.big_src = reinterpret_cast<uint32_t*>(wk + w.big_src);
     d.lmap = reinterpret_cast<uint8_t*>(wk + w.lmap);
     d.gcode = reinterpret_cast<uint8_t*>(wk + w.gcode);
+    d.wet = reinterpret_cast<uint8_t*>(wk + w.wet);
     d.partials = partials ? partials : reinterpret_cast<double*>(wk + w.partials);
     d.ntrav = n_trav(p->L);
     return d;
@@ -674,7 +677,8 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
     }
     const size_t desc_bytes = align_up(n * sizeof(Desc));
     const size_t pre_bytes = align_up(pre.size() * sizeof(uint32_t));
-    const size_t part_bytes = align_up((size_t)n * pl->fv1_grid * hw::kPartial * sizeof(double));
+    const size_t part_bytes =
+        align_up(2 * (size_t)n * pl->fv1_grid * hw::kPartial * sizeof(double));
     hipError_t e = hipMalloc(&pl->dmem, desc_bytes + pre_bytes + part_bytes);
     if (e != hipSuccess) {
         plan_release(pl);
@@ -685,8 +689,9 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
     uint32_t* d_pre = reinterpret_cast<uint32_t*>(base + desc_bytes);
     pl->d_partials = reinterpret_cast<double*>(base + desc_bytes + pre_bytes);
     for (int i = 0; i < n; ++i)
-        pl->host_desc.push_back(make_desc(&problems[i], &buffers[i],
-                                          pl->d_partials + (size_t)i * pl->fv1_grid * hw::kPartial));
+        pl->host_desc.push_back(make_desc(
+            &problems[i], &buffers[i],
+            pl->d_partials + 2 * (size_t)i * pl->fv1_grid * hw::kPartial));
     const bool single = n == 1;
     for (int k = 0; k < pl->passes; ++k)
         pl->enc_prefix.push_back(single ? nullptr : d_pre + enc_off[k]);

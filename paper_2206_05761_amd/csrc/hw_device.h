@@ -14,6 +14,7 @@ constexpr uint32_t kNone = 0xffffffffu; // "no coarse leaf" marker
 constexpr int kPartial = 8;             // doubles per FV1 partial record
 constexpr int kMaxScen = 64;            // problems per batch
 constexpr int kMaxFv1Grid = 8192;
+constexpr int kLeafBatch = 4;           // leaves per FV1 thread per iteration
 
 // Everything a kernel needs to know about one problem.  Lives in device
 // memory (the workspace for single-problem calls, the plan for batches).
@@ -35,6 +36,7 @@ struct Desc {
     uint32_t* big_src;     // per group: leaf index of a coarser leaf or kNone
     uint8_t* lmap;         // per finest cell: level of the leaf containing it
     uint8_t* gcode;        // per traversal group: walk summary (count pass)
+    uint8_t* wet;          // FV1 wet table: 4 bytes per super-chunk
     double* partials;      // FV1 / ingest partial records, kPartial each
     uint32_t ntrav;        // traversal workgroups of this problem
     uint32_t pad1;

@@ -799,6 +799,8 @@ __device__ inline void acc_flush(Acc& a, double (*red)[kPartial], double* rec)
     acc_reset(a);
 }
 
+// The full FV1 update of one leaf (the heavy kernel's path; waves whose
+// leaves are all dry take fv1_dry_write instead, which gives the same result).
 template <typename T>
 __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
 {
@@ -824,62 +826,18 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
     const int lE = x.lmap[(uint64_t)cE << sh];
     const int lS = x.lmap[(uint64_t)cS << sh];
     const int lN = x.lmap[(uint64_t)cN << sh];
-    // Phase 1: depths only.  The level-m neighbour depth is loaded before its
-    // level is known (the slot always exists); a coarser neighbour (lv < m)
-    // is re-read from its leaf.
-    const T h_own = load_h<T>(x, m, c);
-    T hW = load_h<T>(x, m, cW), hE = load_h<T>(x, m, cE);
-    T hS = load_h<T>(x, m, cS), hN = load_h<T>(x, m, cN);
-    const int nW = lW < m ? lW : m, nE = lE < m ? lE : m;
-    const int nS = lS < m ? lS : m, nN = lN < m ? lN : m;
-    const uint32_t kW = cW >> (2 * (m - nW)), kE = cE >> (2 * (m - nE));
-    const uint32_t kS = cS >> (2 * (m - nS)), kN = cN >> (2 * (m - nN));
-    if (nW < m) hW = load_h<T>(x, nW, kW);
-    if (nE < m) hE = load_h<T>(x, nE, kE);
-    if (nS < m) hS = load_h<T>(x, nS, kS);
-    if (nN < m) hN = load_h<T>(x, nN, kN);
-    if (!inW) hW = h_own;
-    if (!inE) hE = h_own;
-    if (!inS) hS = h_own;
-    if (!inN) hN = h_own;
-
-    // Exact dry shortcut: with the cell and its four neighbours dry every
-    // face flux is zero, so h - rx*(0-0) - ry*(0-0) = h; with no rain and no
-    // inflow on the cell the depth stays <= h_tol and the discharges are
-    // reset to zero.  Taken only when it holds on the whole wave.
-    bool inflow_here = false;
-    if (!inW && x.q_peak > 0.0) {
-        const double y_lo = (double)compact1by1(c >> 1) * dym;
-        const double lo = y_lo > x.inlet_y0 ? y_lo : x.inlet_y0;
-        const double yhi = y_lo + dym;
-        const double hi = yhi < x.inlet_y1 ? yhi : x.inlet_y1;
-        inflow_here = hi - lo > 0.0 && inflow_rate(x, x.t) != 0.0;
-    }
-    const bool dry5 = h_own <= tol && hW <= tol && hE <= tol && hS <= tol && hN <= tol;
+    const Cell<T> own = load_cell<T>(x, m, c);
+    const Cell<T> sW = load_cell<T>(x, m, cW);
+    const Cell<T> sE = load_cell<T>(x, m, cE);
+    const Cell<T> sS = load_cell<T>(x, m, cS);
+    const Cell<T> sN = load_cell<T>(x, m, cN);
+    const Cell<T> w = inW ? neighbour_fix<T>(x, m, cW, lW, sW) : ghost_cell<T>(x, HW_W, own);
+    const Cell<T> e = inE ? neighbour_fix<T>(x, m, cE, lE, sE) : ghost_cell<T>(x, HW_E, own);
+    const Cell<T> so = inS ? neighbour_fix<T>(x, m, cS, lS, sS) : ghost_cell<T>(x, HW_S, own);
+    const Cell<T> no = inN ? neighbour_fix<T>(x, m, cN, lN, sN) : ghost_cell<T>(x, HW_N, own);
     const int sh2 = sh;
     const uint64_t f0 = (uint64_t)c << sh2;
     const uint32_t cnt = m >= x.Lg ? (1u << sh2) : 1u;
-    if (!wave_any(!(dry5 && !inflow_here)) && x.rain_rate == 0.0) {
-        store_run<T>(x.fout[0] + f0, cnt, h_own);
-        store_run<T>(x.fout[1] + f0, cnt, T(0));
-        store_run<T>(x.fout[2] + f0, cnt, T(0));
-        acc_max(acc, 1, fabs((double)h_own));
-        acc.v[4] += ((double)h_own * dxm) * dym;
-        return;
-    }
-
-    // Phase 2: discharges and beds of the five states.
-    Cell<T> own, w, e, so, no;
-    own.h = h_own;
-    load_rest<T>(x, m, c, own);
-    w.h = hW;
-    e.h = hE;
-    so.h = hS;
-    no.h = hN;
-    if (inW) load_rest<T>(x, nW, kW, w); else w = ghost_cell<T>(x, HW_W, own);
-    if (inE) load_rest<T>(x, nE, kE, e); else e = ghost_cell<T>(x, HW_E, own);
-    if (inS) load_rest<T>(x, nS, kS, so); else so = ghost_cell<T>(x, HW_S, own);
-    if (inN) load_rest<T>(x, nN, kN, no); else no = ghost_cell<T>(x, HW_N, own);
 
     // Velocities only matter on faces with a wet side; a wave whose five
     // states are all dry skips the divisions (values stay 0 and unused).
@@ -966,49 +924,207 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
         acc.v[6] = 1.0;
 }
 
+// Phase 1 of a leaf for the multi-leaf loop: its depth and its four
+// neighbours' depths; dry is true when the dry shortcut holds for this leaf
+// (cell and neighbours dry, no inflow on it; rain is checked per problem).
+template <typename T>
+struct Probe {
+    T h;
+    uint32_t c;
+    int m;
+    bool dry;
+};
+
+template <typename T>
+__device__ inline Probe<T> fv1_probe(const Fv1Ctx<T>& x, uint32_t idx)
+{
+    Probe<T> p;
+    const int L = x.L;
+    const int m = level_of(idx);
+    const uint32_t c = idx - (uint32_t)level_off(m);
+    const T tol = (T)x.h_tol;
+    const uint32_t lvmask = m > 0 ? (0xffffffffu >> (32 - 2 * m)) : 0u;
+    const uint32_t xm = 0x55555555u & lvmask, ym = 0xaaaaaaaau & lvmask;
+    const int sh = 2 * (L - m);
+    const bool inW = (c & xm) != 0, inE = (c & xm) != xm;
+    const bool inS = (c & ym) != 0, inN = (c & ym) != ym;
+    const uint32_t cW = inW ? morton_xm(c, xm, ym) : c;
+    const uint32_t cE = inE ? morton_xp(c, xm, ym) : c;
+    const uint32_t cS = inS ? morton_ym(c, xm, ym) : c;
+    const uint32_t cN = inN ? morton_yp(c, xm, ym) : c;
+    const int lW = x.lmap[(uint64_t)cW << sh];
+    const int lE = x.lmap[(uint64_t)cE << sh];
+    const int lS = x.lmap[(uint64_t)cS << sh];
+    const int lN = x.lmap[(uint64_t)cN << sh];
+    const T h_own = load_h<T>(x, m, c);
+    T hW = load_h<T>(x, m, cW), hE = load_h<T>(x, m, cE);
+    T hS = load_h<T>(x, m, cS), hN = load_h<T>(x, m, cN);
+    if (lW < m) hW = load_h<T>(x, lW, cW >> (2 * (m - lW)));
+    if (lE < m) hE = load_h<T>(x, lE, cE >> (2 * (m - lE)));
+    if (lS < m) hS = load_h<T>(x, lS, cS >> (2 * (m - lS)));
+    if (lN < m) hN = load_h<T>(x, lN, cN >> (2 * (m - lN)));
+    if (!inW) hW = h_own;
+    if (!inE) hE = h_own;
+    if (!inS) hS = h_own;
+    if (!inN) hN = h_own;
+    bool inflow_here = false;
+    if (!inW && x.q_peak > 0.0) {
+        const double dym = ldexp(x.dy, L - m);
+        const double y_lo = (double)compact1by1(c >> 1) * dym;
+        const double lo = y_lo > x.inlet_y0 ? y_lo : x.inlet_y0;
+        const double yhi = y_lo + dym;
+        const double hi = yhi < x.inlet_y1 ? yhi : x.inlet_y1;
+        inflow_here = hi - lo > 0.0 && inflow_rate(x, x.t) != 0.0;
+    }
+    p.h = h_own;
+    p.c = c;
+    p.m = m;
+    p.dry = h_own <= tol && hW <= tol && hE <= tol && hS <= tol && hN <= tol &&
+            !inflow_here;
+    return p;
+}
+
+// The dry shortcut's result (identical to the full update, see fv1_leaf).
+template <typename T>
+__device__ inline void fv1_dry_write(const Fv1Ctx<T>& x, const Probe<T>& p, Acc& acc)
+{
+    const int sh = 2 * (x.L - p.m);
+    const uint64_t f0 = (uint64_t)p.c << sh;
+    const uint32_t cnt = p.m >= x.Lg ? (1u << sh) : 1u;
+    store_run<T>(x.fout[0] + f0, cnt, p.h);
+    store_run<T>(x.fout[1] + f0, cnt, T(0));
+    store_run<T>(x.fout[2] + f0, cnt, T(0));
+    acc_max(acc, 1, fabs((double)p.h));
+    acc.v[4] += ((double)p.h * ldexp(x.dx, x.L - p.m)) * ldexp(x.dy, x.L - p.m);
+}
+
 // Persistent FV1 kernel over the leaves of n problems.  The leaves of every
 // problem are cut into chunks of kBlock; the chunk sequence of all problems
 // is split into 8 contiguous segments, one per XCD (workgroups are dispatched
 // to XCDs round-robin), so that neighbouring leaves share an L2.  Each
 // workgroup leaves one partial record per problem.
-template <typename T, int MINW>
-__global__ __launch_bounds__(kBlock, MINW) void k_fv1(const Desc* descs, int n)
+// Chunk bookkeeping shared by the two FV1 kernels: the leaves of every
+// problem are cut into super-chunks of kLeafBatch * kBlock leaves; the
+// super-chunk sequence of all problems is split into 8 contiguous segments,
+// one per XCD (workgroups are dispatched to XCDs round-robin), so that
+// neighbouring leaves share an L2.
+struct Fv1Sched {
+    uint32_t c_begin, c_end, g8;
+};
+
+__device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre)
 {
-    __shared__ uint32_t cpre[kMaxScen + 1];
-    __shared__ double rec[kMaxScen][kPartial];
-    __shared__ double red[kBlock / kWave][kPartial];
-    __shared__ double rxy[2 * (HW_MAX_L + 1)];
-    const int tid = threadIdx.x;
-    if (tid == 0) {
+    constexpr uint32_t SC = kLeafBatch * kBlock;
+    if (threadIdx.x == 0) {
         uint32_t a = 0;
         for (int s = 0; s < n; ++s) {
             cpre[s] = a;
             const hw_scalars* sc = descs[s].scal;
             const uint32_t nl = sc->done ? 0u : (uint32_t)sc->n_leaves;
-            a += (nl + kBlock - 1) / kBlock;
+            a += (nl + SC - 1) / SC;
         }
         cpre[n] = a;
     }
-    for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
     __syncthreads();
     const uint32_t total = uniform(cpre[n]);
-    const uint32_t xcd = blockIdx.x & 7u;
-    const uint32_t rank = blockIdx.x >> 3;
-    const uint32_t g8 = gridDim.x >> 3;
+    Fv1Sched f;
+    f.g8 = gridDim.x >> 3;
     const uint32_t seg = (total + 7u) / 8u;
-    const uint32_t c_begin = xcd * seg;
-    const uint32_t c_end = c_begin + seg < total ? c_begin + seg : total;
+    f.c_begin = (blockIdx.x & 7u) * seg + (blockIdx.x >> 3);
+    const uint32_t e = (blockIdx.x & 7u) * seg + seg;
+    f.c_end = e < total ? e : total;
+    return f;
+}
 
+// FV1, light kernel: every leaf's depth probe; waves whose leaves are all
+// dry (no rain, no inflow on them) are finished here; the others are marked
+// in the wet table (one nibble per super-chunk and wave, bit u for the
+// wave's u-th sub-chunk) for the heavy kernel.  Records go to slots
+// [0, gridDim.x).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* descs, int n)
+{
+    constexpr int U = kLeafBatch;
+    constexpr uint32_t SC = U * kBlock;
+    __shared__ uint32_t cpre[kMaxScen + 1];
+    __shared__ double rec[kMaxScen][kPartial];
+    __shared__ double red[kBlock / kWave][kPartial];
+    const int tid = threadIdx.x;
+    const int wid = tid / kWave;
+    for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
+    const Fv1Sched f = fv1_schedule(descs, n, cpre);
     Acc acc;
     acc_reset(acc);
     int cs = -1;
     Fv1Ctx<T> x;
-    uint32_t c0 = 0, c1 = 0;   // chunk range of the current problem
-    // the leaf index of the next chunk (same problem) is loaded one
-    // iteration ahead, so its latency overlaps the current leaf
-    uint32_t next_idx = 0;
-    bool next_ok = false;
-    for (uint32_t ch = c_begin + rank; ch < c_end; ch += g8) {
+    uint32_t c0 = 0, c1 = 0;
+    gp<uint8_t> wetb = gp<uint8_t>(nullptr);
+    for (uint32_t ch = f.c_begin; ch < f.c_end; ch += f.g8) {
+        if (cs < 0 || ch >= c1) {
+            int s = cs < 0 ? 0 : cs;
+            while (cpre[s + 1] <= ch) ++s;
+            s = uniform(s);
+            if (cs >= 0) acc_flush(acc, red, rec[cs]);
+            cs = s;
+            make_ctx<T>(x, descs[s]);
+            wetb = glob(descs[s].wet);
+            c0 = uniform(cpre[s]);
+            c1 = uniform(cpre[s + 1]);
+        }
+        const uint32_t sc = ch - c0;
+        const uint32_t base = sc * SC;
+        uint32_t idx[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t leaf = base + (uint32_t)u * kBlock + tid;
+            ok[u] = leaf < x.nl;
+            idx[u] = ok[u] ? x.leaves[leaf] : 0u;
+        }
+        Probe<T> pr[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pr[u] = fv1_probe<T>(x, idx[u]);
+        uint32_t bits = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool wet = x.rain_rate != 0.0 || wave_any(ok[u] && !pr[u].dry);
+            if (wet) bits |= 1u << u;
+            else if (ok[u]) fv1_dry_write<T>(x, pr[u], acc);
+        }
+        if ((tid & (kWave - 1)) == 0) wetb[4ull * sc + wid] = (uint8_t)bits;
+    }
+    if (cs >= 0) acc_flush(acc, red, rec[cs]);
+    __syncthreads();
+    for (int q = tid; q < n * kPartial; q += kBlock) {
+        const int s = q / kPartial;
+        descs[s].partials[(uint64_t)blockIdx.x * kPartial + q % kPartial] =
+            rec[s][q % kPartial];
+    }
+}
+
+// FV1, heavy kernel: the full update of the wave-chunks the light kernel
+// marked wet, same schedule; super-chunks without a wet wave are skipped
+// after one (uniform) read of their wet word, the next word being read one
+// iteration ahead.  Records go to slots [gridDim.x, 2 gridDim.x).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* descs, int n)
+{
+    constexpr uint32_t SC = kLeafBatch * kBlock;
+    __shared__ uint32_t cpre[kMaxScen + 1];
+    __shared__ double rec[kMaxScen][kPartial];
+    __shared__ double red[kBlock / kWave][kPartial];
+    __shared__ double rxy[2 * (HW_MAX_L + 1)];
+    const int tid = threadIdx.x;
+    const int wid = tid / kWave;
+    for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
+    const Fv1Sched f = fv1_schedule(descs, n, cpre);
+    Acc acc;
+    acc_reset(acc);
+    int cs = -1;
+    Fv1Ctx<T> x;
+    uint32_t c0 = 0, c1 = 0;
+    gp<const uint8_t> wetb = gp<const uint8_t>(nullptr);
+    for (uint32_t ch = f.c_begin; ch < f.c_end; ch += f.g8) {
         if (cs < 0 || ch >= c1) {
             int s = cs < 0 ? 0 : cs;
             while (cpre[s + 1] <= ch) ++s;
@@ -1019,28 +1135,27 @@ __global__ __launch_bounds__(kBlock, MINW) void k_fv1(const Desc* descs, int n)
             fill_rxy(rxy, descs[s], x.dt);
             __syncthreads();
             x.rxy = rxy;
+            wetb = glob(static_cast<const uint8_t*>(descs[s].wet));
             c0 = uniform(cpre[s]);
             c1 = uniform(cpre[s + 1]);
-            next_ok = false;
         }
-        const uint32_t leaf = (ch - c0) * kBlock + tid;
-        uint32_t idx = 0;
-        if (leaf < x.nl) idx = next_ok ? next_idx : x.leaves[leaf];
-        const uint32_t nch = ch + g8;
-        next_ok = false;
-        if (nch < c_end && nch < c1) {
-            const uint32_t nleaf = (nch - c0) * kBlock + tid;
-            if (nleaf < x.nl) {
-                next_idx = x.leaves[nleaf];
-                next_ok = true;
-            }
+        const uint32_t sc = ch - c0;
+        const uint32_t word = uniform(*reinterpret_cast<gp<const uint32_t>>(wetb + 4ull * sc));
+        if (word == 0u) continue;
+        const uint32_t mine = (word >> (8 * wid)) & 0xfu;
+        const uint32_t base = sc * SC;
+#pragma unroll 1
+        for (int u = 0; u < kLeafBatch; ++u) {
+            if (!((mine >> u) & 1u)) continue;
+            const uint32_t leaf = base + (uint32_t)u * kBlock + tid;
+            if (leaf < x.nl) fv1_leaf<T>(x, x.leaves[leaf], acc);
         }
-        if (leaf < x.nl) fv1_leaf<T>(x, idx, acc);
     }
     if (cs >= 0) acc_flush(acc, red, rec[cs]);
+    __syncthreads();
     for (int q = tid; q < n * kPartial; q += kBlock) {
         const int s = q / kPartial;
-        descs[s].partials[(uint64_t)blockIdx.x * kPartial + q % kPartial] =
+        descs[s].partials[((uint64_t)gridDim.x + blockIdx.x) * kPartial + q % kPartial] =
             rec[s][q % kPartial];
     }
 }
@@ -1311,23 +1426,17 @@ hipError_t launch_traverse(Launch lc, uint32_t nblocks, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T>
-static void launch_fv1_t(const Desc* descs, int n, uint32_t grid, int waves,
-                         hipStream_t s)
-{
-    switch (waves) {
-    case 5: hipLaunchKernelGGL((k_fv1<T, 5>), dim3(grid), dim3(kBlock), 0, s, descs, n); break;
-    case 6: hipLaunchKernelGGL((k_fv1<T, 6>), dim3(grid), dim3(kBlock), 0, s, descs, n); break;
-    case 8: hipLaunchKernelGGL((k_fv1<T, 8>), dim3(grid), dim3(kBlock), 0, s, descs, n); break;
-    default: hipLaunchKernelGGL((k_fv1<T, 1>), dim3(grid), dim3(kBlock), 0, s, descs, n); break;
-    }
-}
-
 hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
                            int waves, hipStream_t s)
 {
-    if (prec == HW_FP64) launch_fv1_t<double>(descs, n, grid, waves, s);
-    else launch_fv1_t<float>(descs, n, grid, waves, s);
+    (void)waves;
+    if (prec == HW_FP64) {
+        hipLaunchKernelGGL(k_fv1_light<double>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+        hipLaunchKernelGGL(k_fv1_heavy<double>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+    } else {
+        hipLaunchKernelGGL(k_fv1_light<float>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+        hipLaunchKernelGGL(k_fv1_heavy<float>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+    }
     return hipGetLastError();
 }
 
@@ -1342,7 +1451,7 @@ hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, hipStream_t 
 
 hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(n), dim3(kBlock), 0, s, descs, (int)grid);
+    hipLaunchKernelGGL(k_finalize, dim3(n), dim3(kBlock), 0, s, descs, (int)(2 * grid));
     return hipGetLastError();
 }
 
