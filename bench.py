@@ -76,13 +76,17 @@ def phase_bytes(L, w, hist):
     }
 
 
-def time_single(hw, w, precision, steps, warmup, prof_steps):
+def time_single(hw, w, precision, steps, warmup, prof_steps, tuning=None):
     import torch
     from paper_2206_05761_amd.autotune import autotune
     log(f"[bench] {w.name} {precision}: ingest")
     sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision=precision)
-    best, table = autotune([sim.problem], [sim.buffers], use_cache=False)
-    log(f"[bench] {precision}: autotuned {best}")
+    if tuning is None:
+        best, table = autotune([sim.problem], [sim.buffers], use_cache=False)
+        log(f"[bench] {precision}: autotuned {best}")
+    else:
+        best, table = dict(tuning), None
+        log(f"[bench] {precision}: fixed tuning {best}")
     plan = hw.Plan([sim.problem], [sim.buffers], tuning=best)
     hw.hwfv1_run(sim.problem, sim.buffers, warmup, plan=plan, stats=True)
     s0 = sim.scalars()
@@ -222,6 +226,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--tuning", default=None, metavar="CPT,GRID",
+                    help="fixed launch shape for the single-problem runs "
+                         "(encode cells per thread, FV1 workgroups) instead of "
+                         "the autotuner, e.g. 4,2048")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB three "
                          "times (reference kernel for HBM counter scaling)")
@@ -241,9 +249,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     hw.lib()
+    tuning = None
+    if args.tuning:
+        cpt, grid = (int(v) for v in args.tuning.split(","))
+        tuning = dict(encode_cells_per_thread=cpt, fv1_grid=grid)
     w = W.hydrograph_l12()
     L = w.L
-    r64 = time_single(hw, w, "fp64", args.steps, args.warmup, args.prof_steps)
+    r64 = time_single(hw, w, "fp64", args.steps, args.warmup, args.prof_steps, tuning)
     value = args.steps / (r64["ms"] * 1e-3)
     line = {
         "metric": METRIC,
@@ -269,7 +281,8 @@ def main():
         "tuning": r64["tuning"], "autotune_ms_per_step": r64["tuning_table"],
     }
     if not args.no_fp32:
-        r32 = time_single(hw, w, "fp32_bulk", args.steps, args.warmup, args.prof_steps)
+        r32 = time_single(hw, w, "fp32_bulk", args.steps, args.warmup, args.prof_steps,
+                          tuning)
         line["fp32_bulk"] = {
             "value": round(args.steps / (r32["ms"] * 1e-3), 2), "unit": "timesteps/s",
             "ms_per_step": round(r32["ms"] / args.steps, 5),

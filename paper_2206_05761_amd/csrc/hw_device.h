@@ -116,6 +116,15 @@ __device__ inline int level_of(uint32_t idx)
 template <typename T>
 using gp = T __attribute__((address_space(1)))*;
 
+// Load at a 32-bit byte offset from a (uniform) base: lets the compiler use
+// the scalar-base + 32-bit vector-offset addressing form instead of a 64-bit
+// address per lane.  Every array indexed this way is below 4 GiB.
+template <typename T>
+__device__ inline T ld_off(gp<const T> base, uint32_t byte_off)
+{
+    return *reinterpret_cast<gp<const T>>(reinterpret_cast<gp<const char>>(base) + byte_off);
+}
+
 // Native vector types (usable through global pointers).
 typedef double vd2 __attribute__((ext_vector_type(2)));
 typedef float vf4 __attribute__((ext_vector_type(4)));

@@ -924,90 +924,127 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
         acc.v[6] = 1.0;
 }
 
-// Phase 1 of a leaf for the multi-leaf loop: its depth and its four
-// neighbours' depths; dry is true when the dry shortcut holds for this leaf
-// (cell and neighbours dry, no inflow on it; rain is checked per problem).
+// Pointer to the depth of the hierarchy cell (n, k): the finest set for
+// n = L, the coarse levels otherwise.
 template <typename T>
-struct Probe {
-    T h;
-    uint32_t c;
-    int m;
-    bool dry;
+__device__ inline gp<const T> h_ptr(const Fv1Ctx<T>& x, int n, uint32_t k)
+{
+    return n == x.L ? x.fin[0] + k : x.crs[0] + (level_off(n) + k);
+}
+
+// True when the west-edge inflow adds water to leaf (m, c) at time t.
+template <typename T>
+__device__ inline bool inflow_on(const Fv1Ctx<T>& x, int m, uint32_t c)
+{
+    const uint32_t lvmask = m > 0 ? (0xffffffffu >> (32 - 2 * m)) : 0u;
+    if ((c & 0x55555555u & lvmask) != 0 || !(x.q_peak > 0.0)) return false;
+    const double dym = ldexp(x.dy, x.L - m);
+    const double y_lo = (double)compact1by1(c >> 1) * dym;
+    const double lo = y_lo > x.inlet_y0 ? y_lo : x.inlet_y0;
+    const double yhi = y_lo + dym;
+    const double hi = yhi < x.inlet_y1 ? yhi : x.inlet_y1;
+    return hi - lo > 0.0 && inflow_rate(x, x.t) != 0.0;
+}
+
+// Dry-shortcut probe of kLeafBatch leaves per thread: each leaf's depth and
+// the depths its four faces see (same-level cell, or the coarser leaf that
+// contains it; the cell itself beyond the domain edge, as both ghost kinds
+// copy the depth).  All leaves' loads are issued before any is consumed:
+// first the leaf indices, then every leaf-level byte and depth at once, then,
+// only in waves that have a coarser neighbour, the coarser depths.  The
+// shortcut holds when all five depths are at most h_tol and no inflow
+// reaches the leaf: the full update then leaves h unchanged, sets both
+// discharges to 0 and adds no wave speed (fv1_leaf's result in that case).
+template <typename T>
+struct LightBatch {
+    T h[kLeafBatch];
+    uint32_t c[kLeafBatch];
+    int m[kLeafBatch];
+    bool dry[kLeafBatch];
 };
 
+// Leaf indices of one super-chunk (tail lanes repeat the last leaf).
 template <typename T>
-__device__ inline Probe<T> fv1_probe(const Fv1Ctx<T>& x, uint32_t idx)
+__device__ inline void light_indices(const Fv1Ctx<T>& x, uint32_t base, uint32_t idx[kLeafBatch])
 {
-    Probe<T> p;
-    const int L = x.L;
-    const int m = level_of(idx);
-    const uint32_t c = idx - (uint32_t)level_off(m);
-    const T tol = (T)x.h_tol;
-    const uint32_t lvmask = m > 0 ? (0xffffffffu >> (32 - 2 * m)) : 0u;
-    const uint32_t xm = 0x55555555u & lvmask, ym = 0xaaaaaaaau & lvmask;
-    const int sh = 2 * (L - m);
-    const bool inW = (c & xm) != 0, inE = (c & xm) != xm;
-    const bool inS = (c & ym) != 0, inN = (c & ym) != ym;
-    const uint32_t cW = inW ? morton_xm(c, xm, ym) : c;
-    const uint32_t cE = inE ? morton_xp(c, xm, ym) : c;
-    const uint32_t cS = inS ? morton_ym(c, xm, ym) : c;
-    const uint32_t cN = inN ? morton_yp(c, xm, ym) : c;
-    const int lW = x.lmap[(uint64_t)cW << sh];
-    const int lE = x.lmap[(uint64_t)cE << sh];
-    const int lS = x.lmap[(uint64_t)cS << sh];
-    const int lN = x.lmap[(uint64_t)cN << sh];
-    const T h_own = load_h<T>(x, m, c);
-    T hW = load_h<T>(x, m, cW), hE = load_h<T>(x, m, cE);
-    T hS = load_h<T>(x, m, cS), hN = load_h<T>(x, m, cN);
-    if (lW < m) hW = load_h<T>(x, lW, cW >> (2 * (m - lW)));
-    if (lE < m) hE = load_h<T>(x, lE, cE >> (2 * (m - lE)));
-    if (lS < m) hS = load_h<T>(x, lS, cS >> (2 * (m - lS)));
-    if (lN < m) hN = load_h<T>(x, lN, cN >> (2 * (m - lN)));
-    if (!inW) hW = h_own;
-    if (!inE) hE = h_own;
-    if (!inS) hS = h_own;
-    if (!inN) hN = h_own;
-    bool inflow_here = false;
-    if (!inW && x.q_peak > 0.0) {
-        const double dym = ldexp(x.dy, L - m);
-        const double y_lo = (double)compact1by1(c >> 1) * dym;
-        const double lo = y_lo > x.inlet_y0 ? y_lo : x.inlet_y0;
-        const double yhi = y_lo + dym;
-        const double hi = yhi < x.inlet_y1 ? yhi : x.inlet_y1;
-        inflow_here = hi - lo > 0.0 && inflow_rate(x, x.t) != 0.0;
+#pragma unroll
+    for (int u = 0; u < kLeafBatch; ++u) {
+        uint32_t leaf = base + (uint32_t)u * kBlock + threadIdx.x;
+        leaf = leaf < x.nl ? leaf : x.nl - 1u;
+        idx[u] = ld_off(x.leaves, leaf * 4u);
     }
-    p.h = h_own;
-    p.c = c;
-    p.m = m;
-    p.dry = h_own <= tol && hW <= tol && hE <= tol && hS <= tol && hN <= tol &&
-            !inflow_here;
-    return p;
+}
+
+template <typename T>
+__device__ inline void light_probe(const Fv1Ctx<T>& x, const uint32_t idx[kLeafBatch],
+                                   LightBatch<T>& b)
+{
+    constexpr int U = kLeafBatch;
+    const int L = x.L;
+    const T tol = (T)x.h_tol;
+    uint32_t nb[U][4];
+    int lv[U][4];
+    T hh[U][5];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int m = level_of(idx[u]);
+        const uint32_t c = idx[u] - (uint32_t)level_off(m);
+        b.m[u] = m;
+        b.c[u] = c;
+        const uint32_t lvmask = m > 0 ? (0xffffffffu >> (32 - 2 * m)) : 0u;
+        const uint32_t xm = 0x55555555u & lvmask, ym = 0xaaaaaaaau & lvmask;
+        nb[u][0] = (c & xm) != 0 ? morton_xm(c, xm, ym) : c;
+        nb[u][1] = (c & xm) != xm ? morton_xp(c, xm, ym) : c;
+        nb[u][2] = (c & ym) != 0 ? morton_ym(c, xm, ym) : c;
+        nb[u][3] = (c & ym) != ym ? morton_yp(c, xm, ym) : c;
+        const int sh = 2 * (L - m);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lv[u][k] = ld_off(x.lmap, nb[u][k] << sh);
+        hh[u][0] = *h_ptr<T>(x, m, c);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) hh[u][k + 1] = *h_ptr<T>(x, m, nb[u][k]);
+    }
+    bool coarser = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) coarser = coarser || lv[u][k] < b.m[u];
+    if (wave_any(coarser)) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (lv[u][k] < b.m[u])
+                    hh[u][k + 1] = *h_ptr<T>(x, lv[u][k], nb[u][k] >> (2 * (b.m[u] - lv[u][k])));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        b.h[u] = hh[u][0];
+        b.dry[u] = hh[u][0] <= tol && hh[u][1] <= tol && hh[u][2] <= tol &&
+                   hh[u][3] <= tol && hh[u][4] <= tol && !inflow_on<T>(x, b.m[u], b.c[u]);
+    }
 }
 
 // The dry shortcut's result (identical to the full update, see fv1_leaf).
 template <typename T>
-__device__ inline void fv1_dry_write(const Fv1Ctx<T>& x, const Probe<T>& p, Acc& acc)
+__device__ inline void fv1_dry_write(const Fv1Ctx<T>& x, int m, uint32_t c, T h, Acc& acc)
 {
-    const int sh = 2 * (x.L - p.m);
-    const uint64_t f0 = (uint64_t)p.c << sh;
-    const uint32_t cnt = p.m >= x.Lg ? (1u << sh) : 1u;
-    store_run<T>(x.fout[0] + f0, cnt, p.h);
+    const int sh = 2 * (x.L - m);
+    const uint64_t f0 = (uint64_t)c << sh;
+    const uint32_t cnt = m >= x.Lg ? (1u << sh) : 1u;
+    store_run<T>(x.fout[0] + f0, cnt, h);
     store_run<T>(x.fout[1] + f0, cnt, T(0));
     store_run<T>(x.fout[2] + f0, cnt, T(0));
-    acc_max(acc, 1, fabs((double)p.h));
-    acc.v[4] += ((double)p.h * ldexp(x.dx, x.L - p.m)) * ldexp(x.dy, x.L - p.m);
+    acc_max(acc, 1, fabs((double)h));
+    acc.v[4] += ((double)h * ldexp(x.dx, x.L - m)) * ldexp(x.dy, x.L - m);
 }
 
-// Persistent FV1 kernel over the leaves of n problems.  The leaves of every
-// problem are cut into chunks of kBlock; the chunk sequence of all problems
-// is split into 8 contiguous segments, one per XCD (workgroups are dispatched
-// to XCDs round-robin), so that neighbouring leaves share an L2.  Each
-// workgroup leaves one partial record per problem.
 // Chunk bookkeeping shared by the two FV1 kernels: the leaves of every
 // problem are cut into super-chunks of kLeafBatch * kBlock leaves; the
 // super-chunk sequence of all problems is split into 8 contiguous segments,
 // one per XCD (workgroups are dispatched to XCDs round-robin), so that
-// neighbouring leaves share an L2.
+// neighbouring leaves share an L2.  A workgroup takes every (gridDim.x/8)-th
+// super-chunk of its segment.
 struct Fv1Sched {
     uint32_t c_begin, c_end, g8;
 };
@@ -1036,13 +1073,12 @@ __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre
     return f;
 }
 
-// FV1, light kernel: every leaf's depth probe; waves whose leaves are all
+// FV1, light kernel: every leaf's dry probe; waves whose leaves are all
 // dry (no rain, no inflow on them) are finished here; the others are marked
-// in the wet table (one nibble per super-chunk and wave, bit u for the
-// wave's u-th sub-chunk) for the heavy kernel.  Records go to slots
-// [0, gridDim.x).
+// in the wet table (one byte per super-chunk and wave, bit u for the wave's
+// u-th sub-chunk) for the heavy kernel.  Records go to slots [0, gridDim.x).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* descs, int n)
+__global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ descs, int n)
 {
     constexpr int U = kLeafBatch;
     constexpr uint32_t SC = U * kBlock;
@@ -1074,22 +1110,16 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* descs, int n)
         const uint32_t sc = ch - c0;
         const uint32_t base = sc * SC;
         uint32_t idx[U];
-        bool ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t leaf = base + (uint32_t)u * kBlock + tid;
-            ok[u] = leaf < x.nl;
-            idx[u] = ok[u] ? x.leaves[leaf] : 0u;
-        }
-        Probe<T> pr[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) pr[u] = fv1_probe<T>(x, idx[u]);
+        light_indices<T>(x, base, idx);
+        LightBatch<T> b;
+        light_probe<T>(x, idx, b);
         uint32_t bits = 0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool wet = x.rain_rate != 0.0 || wave_any(ok[u] && !pr[u].dry);
+            const bool ok = base + (uint32_t)u * kBlock + tid < x.nl;
+            const bool wet = x.rain_rate != 0.0 || wave_any(ok && !b.dry[u]);
             if (wet) bits |= 1u << u;
-            else if (ok[u]) fv1_dry_write<T>(x, pr[u], acc);
+            else if (ok) fv1_dry_write<T>(x, b.m[u], b.c[u], b.h[u], acc);
         }
         if ((tid & (kWave - 1)) == 0) wetb[4ull * sc + wid] = (uint8_t)bits;
     }
@@ -1103,59 +1133,80 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* descs, int n)
 }
 
 // FV1, heavy kernel: the full update of the wave-chunks the light kernel
-// marked wet, same schedule; super-chunks without a wet wave are skipped
-// after one (uniform) read of their wet word, the next word being read one
-// iteration ahead.  Records go to slots [gridDim.x, 2 gridDim.x).
+// marked wet.  It runs with its own (smaller, fully resident) grid on the
+// same segment scheme; each wave reads the wet words of up to 64 of its
+// workgroup's super-chunks at once (one per lane), so that a workgroup with
+// no wet super-chunk costs one round trip.  Every wave of a workgroup reads
+// the same words and so visits the same super-chunks, in ascending order.
+// Records go to slots [rec0, rec0 + gridDim.x).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* descs, int n)
+__global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ descs, int n, uint32_t rec0)
 {
     constexpr uint32_t SC = kLeafBatch * kBlock;
     __shared__ uint32_t cpre[kMaxScen + 1];
     __shared__ double rec[kMaxScen][kPartial];
     __shared__ double red[kBlock / kWave][kPartial];
     __shared__ double rxy[2 * (HW_MAX_L + 1)];
+    __shared__ const uint8_t* wtab[kMaxScen];
     const int tid = threadIdx.x;
     const int wid = tid / kWave;
+    const int lane = tid & (kWave - 1);
     for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
-    const Fv1Sched f = fv1_schedule(descs, n, cpre);
+    if (tid < n) wtab[tid] = descs[tid].wet;
+    const Fv1Sched f = fv1_schedule(descs, n, cpre);   // ends with a barrier
+    const uint32_t K = f.c_begin < f.c_end ? (f.c_end - f.c_begin + f.g8 - 1) / f.g8 : 0u;
     Acc acc;
     acc_reset(acc);
     int cs = -1;
     Fv1Ctx<T> x;
     uint32_t c0 = 0, c1 = 0;
-    gp<const uint8_t> wetb = gp<const uint8_t>(nullptr);
-    for (uint32_t ch = f.c_begin; ch < f.c_end; ch += f.g8) {
-        if (cs < 0 || ch >= c1) {
-            int s = cs < 0 ? 0 : cs;
-            while (cpre[s + 1] <= ch) ++s;
-            s = uniform(s);
-            if (cs >= 0) acc_flush(acc, red, rec[cs]);   // ends with a barrier
-            cs = s;
-            make_ctx<T>(x, descs[s]);
-            fill_rxy(rxy, descs[s], x.dt);
-            __syncthreads();
-            x.rxy = rxy;
-            wetb = glob(static_cast<const uint8_t*>(descs[s].wet));
-            c0 = uniform(cpre[s]);
-            c1 = uniform(cpre[s + 1]);
+    for (uint32_t k0 = 0; k0 < K; k0 += kWave) {
+        uint32_t word = 0;
+        const uint32_t kl = k0 + (uint32_t)lane;
+        if (kl < K) {
+            const uint32_t ch = f.c_begin + kl * f.g8;
+            int lo = 0, hi = n - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (cpre[mid] <= ch) lo = mid;
+                else hi = mid - 1;
+            }
+            word = *reinterpret_cast<gp<const uint32_t>>(glob(wtab[lo]) + 4ull * (ch - cpre[lo]));
         }
-        const uint32_t sc = ch - c0;
-        const uint32_t word = uniform(*reinterpret_cast<gp<const uint32_t>>(wetb + 4ull * sc));
-        if (word == 0u) continue;
-        const uint32_t mine = (word >> (8 * wid)) & 0xfu;
-        const uint32_t base = sc * SC;
+        uint64_t mask = __ballot(word != 0u);
+        while (mask) {
+            const int j = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const uint32_t wj = (uint32_t)__builtin_amdgcn_readlane((int)word, j);
+            const uint32_t ch = f.c_begin + (k0 + (uint32_t)j) * f.g8;
+            if (cs < 0 || ch >= c1) {
+                int s = cs < 0 ? 0 : cs;
+                while (cpre[s + 1] <= ch) ++s;
+                s = uniform(s);
+                if (cs >= 0) acc_flush(acc, red, rec[cs]);   // ends with a barrier
+                cs = s;
+                make_ctx<T>(x, descs[s]);
+                fill_rxy(rxy, descs[s], x.dt);
+                __syncthreads();
+                x.rxy = rxy;
+                c0 = uniform(cpre[s]);
+                c1 = uniform(cpre[s + 1]);
+            }
+            const uint32_t mine = (wj >> (8 * wid)) & ((1u << kLeafBatch) - 1u);
+            const uint32_t base = (ch - c0) * SC;
 #pragma unroll 1
-        for (int u = 0; u < kLeafBatch; ++u) {
-            if (!((mine >> u) & 1u)) continue;
-            const uint32_t leaf = base + (uint32_t)u * kBlock + tid;
-            if (leaf < x.nl) fv1_leaf<T>(x, x.leaves[leaf], acc);
+            for (int u = 0; u < kLeafBatch; ++u) {
+                if (!((mine >> u) & 1u)) continue;
+                const uint32_t leaf = base + (uint32_t)u * kBlock + tid;
+                if (leaf < x.nl) fv1_leaf<T>(x, x.leaves[leaf], acc);
+            }
         }
     }
     if (cs >= 0) acc_flush(acc, red, rec[cs]);
     __syncthreads();
     for (int q = tid; q < n * kPartial; q += kBlock) {
         const int s = q / kPartial;
-        descs[s].partials[((uint64_t)gridDim.x + blockIdx.x) * kPartial + q % kPartial] =
+        descs[s].partials[((uint64_t)rec0 + blockIdx.x) * kPartial + q % kPartial] =
             rec[s][q % kPartial];
     }
 }
@@ -1200,8 +1251,30 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Desc* descs,
     if (sc->done) return;
     Acc a;
     acc_reset(a);
-    for (int b = threadIdx.x; b < fv1_grid; b += blockDim.x)
-        acc_add_record(a, d.partials + (uint64_t)b * kPartial);
+    // four records per thread and round, all loaded before any is combined
+    // (a record past the end reads as zeros, the identity of every slot)
+    const gp<const vd2> pr = reinterpret_cast<gp<const vd2>>(glob(d.partials));
+    for (int b0 = threadIdx.x; b0 < fv1_grid; b0 += 4 * blockDim.x) {
+        vd2 r[4][kPartial / 2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int b = b0 + k * (int)blockDim.x;
+            const int bc = b < fv1_grid ? b : fv1_grid - 1;
+#pragma unroll
+            for (int q = 0; q < kPartial / 2; ++q) r[k][q] = pr[(uint64_t)bc * (kPartial / 2) + q];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool ok = b0 + k * (int)blockDim.x < fv1_grid;
+            double v[kPartial];
+#pragma unroll
+            for (int q = 0; q < kPartial / 2; ++q) {
+                v[2 * q] = ok ? r[k][q].x : 0.0;
+                v[2 * q + 1] = ok ? r[k][q].y : 0.0;
+            }
+            acc_add_record(a, v);
+        }
+    }
     __shared__ double tot[kPartial];
     if (threadIdx.x < kPartial) tot[threadIdx.x] = 0.0;
     __syncthreads();
@@ -1426,16 +1499,25 @@ hipError_t launch_traverse(Launch lc, uint32_t nblocks, hipStream_t s)
     return hipGetLastError();
 }
 
+// Workgroups of the heavy FV1 kernel: about as many as are resident at its
+// occupancy (two waves per SIMD), never more than the light kernel's.
+uint32_t heavy_grid(uint32_t grid)
+{
+    constexpr uint32_t kHeavy = 512;
+    return grid < kHeavy ? grid : kHeavy;
+}
+
 hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
                            int waves, hipStream_t s)
 {
     (void)waves;
+    const uint32_t gh = heavy_grid(grid);
     if (prec == HW_FP64) {
         hipLaunchKernelGGL(k_fv1_light<double>, dim3(grid), dim3(kBlock), 0, s, descs, n);
-        hipLaunchKernelGGL(k_fv1_heavy<double>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+        hipLaunchKernelGGL(k_fv1_heavy<double>, dim3(gh), dim3(kBlock), 0, s, descs, n, grid);
     } else {
         hipLaunchKernelGGL(k_fv1_light<float>, dim3(grid), dim3(kBlock), 0, s, descs, n);
-        hipLaunchKernelGGL(k_fv1_heavy<float>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+        hipLaunchKernelGGL(k_fv1_heavy<float>, dim3(gh), dim3(kBlock), 0, s, descs, n, grid);
     }
     return hipGetLastError();
 }
@@ -1451,7 +1533,8 @@ hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, hipStream_t 
 
 hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(n), dim3(kBlock), 0, s, descs, (int)(2 * grid));
+    hipLaunchKernelGGL(k_finalize, dim3(n), dim3(kBlock), 0, s, descs,
+                       (int)(grid + heavy_grid(grid)));
     return hipGetLastError();
 }
 
