@@ -113,7 +113,39 @@ def time_single(hw, w, precision, steps, warmup, prof_steps, tuning=None):
     return res
 
 
-def roofline(res, L, w):
+KERNEL_SOURCES = ["paper_2206_05761_amd/csrc/hw_kernels.hip",
+                  "paper_2206_05761_amd/csrc/hw_device.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def load_traffic(phase, precision):
+    """Measured HBM bytes per launch of a phase's kernels, from the committed
+    rocprofv3 counter summary, or None when there is none or the kernel
+    sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{phase}_hydrograph_l12_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        text = fh.read()
+    for line in text.splitlines():
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    return int(float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]))
+
+
+def roofline(res, L, w, precision=None):
     pb = phase_bytes(L, w, res["hist"])
     prof = res["prof"]
     dom = max((k for k in prof), key=lambda k: prof[k])
@@ -126,7 +158,7 @@ def roofline(res, L, w):
     return {
         "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": load_traffic(dom, precision) if precision else None,
         "algorithmic_bytes": int(pb[dom]),
         "avg_ms": round(prof[dom], 5),
         "step_bytes": int(total_bytes), "step_ms_phases": round(step_ms, 5),
@@ -277,7 +309,7 @@ def main():
                    "manning_n": w.params["manning_n"], "precision": "fp64"},
         "leaf_updates_per_s": r64["leaf_updates"] / (r64["ms"] * 1e-3),
         "n_leaves": int(r64["scalars"]["n_leaves"]),
-        "roofline": roofline(r64, L, 8),
+        "roofline": roofline(r64, L, 8, "fp64"),
         "tuning": r64["tuning"], "autotune_ms_per_step": r64["tuning_table"],
     }
     if not args.no_fp32:
@@ -287,7 +319,7 @@ def main():
             "value": round(args.steps / (r32["ms"] * 1e-3), 2), "unit": "timesteps/s",
             "ms_per_step": round(r32["ms"] / args.steps, 5),
             "leaf_updates_per_s": r32["leaf_updates"] / (r32["ms"] * 1e-3),
-            "roofline": roofline(r32, L, 4),
+            "roofline": roofline(r32, L, 4, "fp32_bulk"),
             "tuning": r32["tuning"],
             "error_vs_fp64": fp32_error(hw, r64, r32),
         }

@@ -150,7 +150,8 @@ typedef struct hw_scalars {
  *   work        scratch of hw_workspace_bytes() bytes, private to the
  *               library; between mra_traverse_leaves and fv1_step it carries
  *               the traversal's fill table and the per-finest-cell leaf
- *               level map (N bytes) that the FV1 neighbour lookup reads
+ *               level map (N bytes) that the FV1 neighbour lookup reads;
+ *               across steps it keeps the FV1 write history (hw_forget)
  */
 typedef struct hw_buffers {
     void* fine[2][3];
@@ -318,6 +319,18 @@ enum {
 };
 int hw_plan_profile(hw_plan* plan, int64_t steps, double* ms_out,
                     hipStream_t stream);
+
+/*
+ * Forget the FV1 write history kept in the work buffer.  The FV1 step skips
+ * the stores of a 64-cell block of finest leaves that the dry case (all
+ * depths <= h_tol, no inflow, no rain) has finished at the two previous
+ * steps, because the set being written then already holds the result; it
+ * learns this from a per-block record of those steps in `work`.  hw_ingest
+ * clears the record.  Call this after writing fine[][] or scal by any other
+ * means (e.g. restoring a saved state) before the next step.  Errors:
+ * HW_EINVAL for a bad problem or buffers, HW_EHIP on launch failure.
+ */
+int hw_forget(const hw_problem* p, const hw_buffers* b, hipStream_t stream);
 
 /*
  * Export the current finest set to row-major FP64 device arrays (N each);

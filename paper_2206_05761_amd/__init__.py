@@ -113,6 +113,7 @@ def lib():
         L.hw_plan_destroy.argtypes = [vp]
         L.hwfv1_run_batch.argtypes = [vp, C.c_int64, P(HwStats), vp]
         L.hw_export.argtypes = [P(HwProblem), P(HwBuffers), vp, vp, vp, vp]
+        L.hw_forget.argtypes = [P(HwProblem), P(HwBuffers), vp]
         L.hw_plan_profile.argtypes = [vp, C.c_int64, P(C.c_double), vp]
         _lib = L
     return _lib
@@ -262,6 +263,11 @@ def mra_traverse_leaves(problem, buffers, stream=None):
 
 def fv1_step(problem, buffers, stream=None):
     _check(lib().fv1_step(C.byref(problem), C.byref(buffers.c), _stream(stream)))
+
+
+def hw_forget(problem, buffers, stream=None):
+    """Forget the FV1 write history (after writing fine sets or scal directly)."""
+    _check(lib().hw_forget(C.byref(problem), C.byref(buffers.c), _stream(stream)))
 
 
 def hw_export(problem, buffers, stream=None):

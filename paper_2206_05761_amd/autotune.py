@@ -5,7 +5,8 @@ Chooses, for a given set of problems (one, or a batch), the encoding tile
 levels fused per pass) and the number of persistent FV1 workgroups, by timing
 each candidate's captured step graph on the problems themselves.  The state
 (both finest sets and the scalars) is saved before and restored after every
-candidate, so tuning leaves the simulation where it was.  Results are cached
+candidate (and the FV1 write history forgotten), so tuning leaves the
+simulation where it was.  Results are cached
 in a JSON file keyed by GPU architecture, precision, batch size and levels.
 """
 import json
@@ -13,7 +14,7 @@ import os
 
 import torch
 
-from . import Plan, hwfv1_run, hwfv1_run_batch
+from . import Plan, hw_forget, hwfv1_run, hwfv1_run_batch
 
 CANDIDATES = [dict(encode_cells_per_thread=c, fv1_grid=g)
               for c in (4, 16) for g in (1024, 2048, 4096)]
@@ -51,13 +52,14 @@ def _snapshot(buffers):
              b.scal.clone()) for b in buffers]
 
 
-def _restore(buffers, snap):
-    for b, (f0, f1, sc) in zip(buffers, snap):
+def _restore(problems, buffers, snap):
+    for p, b, (f0, f1, sc) in zip(problems, buffers, snap):
         for dst, src in zip(b.fine[0], f0):
             dst.copy_(src)
         for dst, src in zip(b.fine[1], f1):
             dst.copy_(src)
         b.scal.copy_(sc)
+        hw_forget(p, b)
 
 
 def _time(problems, buffers, tuning, steps, warmup):
@@ -91,7 +93,7 @@ def autotune(problems, buffers, steps=10, warmup=2, candidates=None,
     results = []
     for cand in candidates or CANDIDATES:
         ms = _time(problems, buffers, cand, steps, warmup)
-        _restore(buffers, snap)
+        _restore(problems, buffers, snap)
         results.append((ms, cand))
     torch.cuda.synchronize()
     results.sort(key=lambda r: r[0])

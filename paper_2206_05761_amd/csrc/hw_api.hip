@@ -35,6 +35,7 @@ hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
                            int waves, hipStream_t s);
 hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, hipStream_t s);
 hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t s);
+hipError_t launch_forget(const Desc* dd, uint64_t nhist, hipStream_t s);
 }  // namespace hw
 
 using hw::Desc;
@@ -97,8 +98,12 @@ uint32_t encode_blocks(int L, int pass, int tl)
 }
 
 struct WorkLayout {
-    size_t desc, tcount, big_src, gcode, lmap, wet, partials, total;
+    size_t desc, tcount, big_src, gcode, lmap, wet, hist, partials, total;
 };
+
+// Entries of the FV1 write history: one per 64-cell Morton block of the
+// finest level (at least one).
+size_t n_hist(int L) { size_t n = (size_t)hw_n_fine_(L) / 64; return n ? n : 1; }
 
 WorkLayout work_layout(int L)
 {
@@ -116,6 +121,8 @@ WorkLayout work_layout(int L)
     o = align_up(o + (size_t)hw_n_fine_(L));
     w.wet = o;
     o = align_up(o + 4 * ((size_t)hw_n_fine_(L) / (hw::kLeafBatch * hw::kBlock) + 1));
+    w.hist = o;
+    o = align_up(o + n_hist(L) * sizeof(uint64_t));
     w.partials = o;
     o = align_up(o + 2 * (size_t)hw::kMaxFv1Grid * hw::kPartial * sizeof(double));
     w.total = o;
@@ -225,6 +232,8 @@ Desc make_desc(const hw_problem* p, const hw_buffers* b, double* partials)
     d.lmap = reinterpret_cast<uint8_t*>(wk + w.lmap);
     d.gcode = reinterpret_cast<uint8_t*>(wk + w.gcode);
     d.wet = reinterpret_cast<uint8_t*>(wk + w.wet);
+    d.hist = reinterpret_cast<uint64_t*>(wk + w.hist);
+    d.nhist = (uint32_t)n_hist(p->L);
     d.partials = partials ? partials : reinterpret_cast<double*>(wk + w.partials);
     d.ntrav = n_trav(p->L);
     return d;
@@ -488,6 +497,8 @@ int hw_ingest(const hw_problem* p, const hw_buffers* b, const double* h,
     if (grid > 2048) grid = 2048;
     hipError_t e = hw::launch_ingest(p->precision, dd, (uint32_t)grid, h, qx, qy, z, stream);
     if (e != hipSuccess) return hip_fail(e, "ingest launch");
+    e = hw::launch_forget(dd, n_hist(p->L), stream);
+    if (e != hipSuccess) return hip_fail(e, "history reset launch");
     const int cp = 1, tl = pass_levels(cp);
     for (int k = 0; k < n_passes(p->L, tl); ++k) {
         e = hw::launch_encode_bed(Launch{dd, nullptr, 1}, encode_blocks(p->L, k, tl), k,
@@ -553,6 +564,16 @@ int fv1_step(const hw_problem* p, const hw_buffers* b, hipStream_t stream)
     hipError_t e = hw::launch_fv1(p->precision, dd, 1, grid, Launch{dd, nullptr, 1},
                                   n_trav(p->L), stream);
     if (e != hipSuccess) return hip_fail(e, "fv1 launch");
+    return ok();
+}
+
+int hw_forget(const hw_problem* p, const hw_buffers* b, hipStream_t stream)
+{
+    Desc d;
+    int rc = prep_single(p, b, stream, &d);
+    if (rc) return rc;
+    hipError_t e = hw::launch_forget(work_desc(b), n_hist(p->L), stream);
+    if (e != hipSuccess) return hip_fail(e, "history reset launch");
     return ok();
 }
 

@@ -37,9 +37,10 @@ struct Desc {
     uint8_t* lmap;         // per finest cell: level of the leaf containing it
     uint8_t* gcode;        // per traversal group: walk summary (count pass)
     uint8_t* wet;          // FV1 wet table: 4 bytes per super-chunk
+    uint64_t* hist;        // FV1 write history: one entry per 64 finest cells
     double* partials;      // FV1 / ingest partial records, kPartial each
     uint32_t ntrav;        // traversal workgroups of this problem
-    uint32_t pad1;
+    uint32_t nhist;        // entries of hist
 };
 
 // Work decomposition of one launch: problem s owns workgroups

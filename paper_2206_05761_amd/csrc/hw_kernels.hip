@@ -95,10 +95,9 @@ __device__ inline void load4(gp<const float> p, double o[4])
 // FLOW: h, qx, qy of the current step (flags OR-ed with the static bed
 // flags into raw); otherwise the bed (flags into zsig).
 
-template <typename T, int NV, bool FLOW, bool DET>
+template <typename T, int NV, bool FLOW, bool DET, int CP>
 __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
-                                                   int tl, int cpt,
-                                                   double* details)
+                                                   int tl, double* details)
 {
     uint32_t b;
     const int s = scen_of(lc, blockIdx.x, b);
@@ -110,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     if (n_in <= 0) return;
     const int lv = n_in < tl ? n_in : tl;
     const int n_lo = n_in - lv;
-    const int cp = cpt < lv ? cpt : lv;
+    const int cp = CP < lv ? CP : lv;   // levels computed in registers
     const int tid = threadIdx.x;
     const uint64_t ncoarse = level_off(L);
 
@@ -170,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     if ((uint32_t)tid < M) {
         const uint64_t tile_in = (uint64_t)b << (2 * lv);
         // All child loads are issued before any store of this thread.
-        if (cp == 1) {
+        if (CP == 1 || cp == 1) {
             const uint64_t base = tile_in + 4ull * tid;
             double ch[NV][4];
 #pragma unroll
@@ -373,10 +372,9 @@ __device__ inline uint32_t walk_code(const Desc& d, uint32_t g)
 // holds its first finest descendant (so each leaf appears once) and is
 // recorded in big for the copy-down; lvl receives the leaf level of each
 // quarter of the group.
-template <bool WRITE>
+template <bool WRITE, typename P>
 __device__ inline int group_leaves(const Desc& d, uint32_t g, uint32_t code,
-                                   gp<uint32_t> out, uint32_t& big,
-                                   uint32_t lvl[4])
+                                   P out, uint32_t& big, uint32_t lvl[4])
 {
     const int Lg = d.group_level;
     const int n1 = Lg + 1;
@@ -461,19 +459,25 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     uint32_t big = kNone;
     uint32_t lvl[4];
     const uint32_t cnt =
-        active ? (uint32_t)group_leaves<false>(d, g, code, gp<uint32_t>(nullptr), big, lvl) : 0u;
+        active ? (uint32_t)group_leaves<false>(d, g, code, (uint32_t*)nullptr, big, lvl) : 0u;
     uint32_t total;
     const uint32_t excl = block_excl_scan(cnt, lds, total);
     if (!EMIT) {
         if (threadIdx.x == 0) glob(d.tcount)[lb] = total;
         return;
     }
+    // The workgroup's leaves are one contiguous run of the list: they are
+    // staged in LDS at their in-workgroup offsets and then written with
+    // consecutive lanes on consecutive entries.
+    __shared__ uint32_t stage[kBlock * 16];
     if (active) {
-        const uint32_t base = glob(d.tcount)[lb] + excl;
-        group_leaves<true>(d, g, code, glob(d.leaves) + base, big, lvl);
+        group_leaves<true>(d, g, code, stage + excl, big, lvl);
         glob(d.big_src)[g] = big;
         write_level_map(d, g, lvl);
     }
+    __syncthreads();
+    const gp<uint32_t> out = glob(d.leaves) + glob(d.tcount)[lb];
+    for (uint32_t i = threadIdx.x; i < total; i += kBlock) out[i] = stage[i];
 }
 
 // Exclusive scan of the per-workgroup leaf counts of one problem (one
@@ -515,6 +519,8 @@ struct Fv1Ctx {
     gp<const double> zh;   // bed hierarchy
     gp<const uint8_t> lmap;
     gp<const uint32_t> leaves;
+    gp<uint64_t> hist;     // write history (light kernel)
+    uint64_t step;         // index of the step being taken
     int L, Lg;
     int bc[4];
     double dx, dy, g, h_tol, manning_n, rain_rate;
@@ -548,6 +554,8 @@ __device__ inline void make_ctx(Fv1Ctx<T>& x, const Desc& d)
     x.zh = glob(static_cast<const double*>(d.zhier));
     x.lmap = glob(static_cast<const uint8_t*>(d.lmap));
     x.leaves = glob(static_cast<const uint32_t*>(d.leaves));
+    x.hist = glob(d.hist);
+    x.step = sc->step;
     x.L = d.L;
     x.Lg = d.group_level;
     for (int k = 0; k < 4; ++k) x.bc[k] = d.bc[k];
@@ -961,6 +969,7 @@ struct LightBatch {
     uint32_t c[kLeafBatch];
     int m[kLeafBatch];
     bool dry[kLeafBatch];
+    uint64_t e[kLeafBatch];   // write-history entry of the wave's first cell's block
 };
 
 // Leaf indices of one super-chunk (tail lanes repeat the last leaf).
@@ -1003,6 +1012,8 @@ __device__ inline void light_probe(const Fv1Ctx<T>& x, const uint32_t idx[kLeafB
         hh[u][0] = *h_ptr<T>(x, m, c);
 #pragma unroll
         for (int k = 0; k < 4; ++k) hh[u][k + 1] = *h_ptr<T>(x, m, nb[u][k]);
+        // c < 4^m <= 4^L, so c / 64 indexes the table even when unused
+        b.e[u] = x.hist[uniform(c) >> 6];
     }
     bool coarser = false;
 #pragma unroll
@@ -1025,18 +1036,47 @@ __device__ inline void light_probe(const Fv1Ctx<T>& x, const uint32_t idx[kLeafB
     }
 }
 
-// The dry shortcut's result (identical to the full update, see fv1_leaf).
+// The dry shortcut's result (identical to the full update, see fv1_leaf);
+// the stores are left out when the set being written already holds it.
 template <typename T>
-__device__ inline void fv1_dry_write(const Fv1Ctx<T>& x, int m, uint32_t c, T h, Acc& acc)
+__device__ inline void fv1_dry_write(const Fv1Ctx<T>& x, int m, uint32_t c, T h, Acc& acc,
+                                     bool store)
 {
-    const int sh = 2 * (x.L - m);
-    const uint64_t f0 = (uint64_t)c << sh;
-    const uint32_t cnt = m >= x.Lg ? (1u << sh) : 1u;
-    store_run<T>(x.fout[0] + f0, cnt, h);
-    store_run<T>(x.fout[1] + f0, cnt, T(0));
-    store_run<T>(x.fout[2] + f0, cnt, T(0));
+    if (store) {
+        const int sh = 2 * (x.L - m);
+        const uint64_t f0 = (uint64_t)c << sh;
+        const uint32_t cnt = m >= x.Lg ? (1u << sh) : 1u;
+        store_run<T>(x.fout[0] + f0, cnt, h);
+        store_run<T>(x.fout[1] + f0, cnt, T(0));
+        store_run<T>(x.fout[2] + f0, cnt, T(0));
+    }
     acc_max(acc, 1, fabs((double)h));
     acc.v[4] += ((double)h * ldexp(x.dx, x.L - m)) * ldexp(x.dy, x.L - m);
+}
+
+// Write history of one wave's 64 leaves (wave-uniform).  When those leaves
+// are the 64 finest cells of one aligned Morton block B, the block's entry
+// records (index of the step + 1) << 2 and, in its two low bits, whether the
+// dry shortcut finished all 64 at the last two steps that updated it.  If it
+// did at steps k-1 and k-2 (entry written at step k-1 with both bits) and
+// does again at step k, the set being written at step k holds state k-1 on
+// B, which is (h, 0, 0) with the h that steps k-1 and k leave unchanged: the
+// result of step k is already in place and its stores are skipped.  Any
+// other writer of B's cells (full update, coarser leaves, a misaligned
+// wave) does not refresh the entry, so its step no longer matches and the
+// next steps store again.  Returns true when the stores may be skipped.
+template <typename T>
+__device__ inline bool light_history(const Fv1Ctx<T>& x, bool ok, int m, uint32_t c,
+                                     bool dry, uint64_t e)
+{
+    const uint32_t c0 = uniform(c);
+    const uint32_t c63 = (uint32_t)__builtin_amdgcn_readlane((int)c, kWave - 1);
+    const bool block = !wave_any(!ok || m != x.L) && (c0 & 63u) == 0u && c63 == c0 + 63u;
+    if (!block) return false;
+    const bool valid = (e >> 2) == x.step;
+    const uint64_t bits = ((valid ? (e << 1) : 0ull) | (dry ? 1ull : 0ull)) & 3ull;
+    if ((threadIdx.x & (kWave - 1)) == 0) x.hist[c0 >> 6] = ((x.step + 1) << 2) | bits;
+    return dry && valid && (e & 3ull) == 3ull;
 }
 
 // Chunk bookkeeping shared by the two FV1 kernels: the leaves of every
@@ -1118,8 +1158,9 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
         for (int u = 0; u < U; ++u) {
             const bool ok = base + (uint32_t)u * kBlock + tid < x.nl;
             const bool wet = x.rain_rate != 0.0 || wave_any(ok && !b.dry[u]);
+            const bool skip = light_history<T>(x, ok, b.m[u], b.c[u], !wet, b.e[u]);
             if (wet) bits |= 1u << u;
-            else if (ok) fv1_dry_write<T>(x, b.m[u], b.c[u], b.h[u], acc);
+            else if (ok) fv1_dry_write<T>(x, b.m[u], b.c[u], b.h[u], acc, !skip);
         }
         if ((tid & (kWave - 1)) == 0) wetb[4ull * sc + wid] = (uint8_t)bits;
     }
@@ -1242,10 +1283,12 @@ __global__ __launch_bounds__(kBlock) void k_fill(Launch lc)
 // One workgroup per problem: combine the FV1 partial records, then advance
 // t, choose the next CFL timestep (capped at dt_max, shortened to hit
 // t_end), update s_max, mass and counters, and flip the finest set.
-__global__ __launch_bounds__(kBlock) void k_finalize(const Desc* descs,
-                                                     int fv1_grid)
+constexpr int kFinalBlock = 1024;
+
+__global__ __launch_bounds__(kFinalBlock) void k_finalize(const Desc* descs,
+                                                          int fv1_grid)
 {
-    __shared__ double red[kBlock / kWave][kPartial];
+    __shared__ double red[kFinalBlock / kWave][kPartial];
     const Desc& d = descs[blockIdx.x];
     hw_scalars* sc = d.scal;
     if (sc->done) return;
@@ -1450,28 +1493,36 @@ hipError_t launch_ingest(int prec, const Desc* dd, uint32_t grid,
 hipError_t launch_encode_bed(Launch lc, uint32_t nblocks, int pass, int tl,
                              int cpt, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_encode<double, 1, false, false>), dim3(nblocks),
-                       dim3(kBlock), 0, s, lc, pass, tl, cpt, (double*)nullptr);
+    if (cpt == 2)
+        hipLaunchKernelGGL((k_encode<double, 1, false, false, 2>), dim3(nblocks),
+                           dim3(kBlock), 0, s, lc, pass, tl, (double*)nullptr);
+    else
+        hipLaunchKernelGGL((k_encode<double, 1, false, false, 1>), dim3(nblocks),
+                           dim3(kBlock), 0, s, lc, pass, tl, (double*)nullptr);
     return hipGetLastError();
+}
+
+template <typename T, bool DET>
+static void encode_flow_t(Launch lc, uint32_t nblocks, int pass, int tl, int cpt,
+                          double* details, hipStream_t s)
+{
+    if (cpt == 2)
+        hipLaunchKernelGGL((k_encode<T, 3, true, DET, 2>), dim3(nblocks), dim3(kBlock), 0, s,
+                           lc, pass, tl, details);
+    else
+        hipLaunchKernelGGL((k_encode<T, 3, true, DET, 1>), dim3(nblocks), dim3(kBlock), 0, s,
+                           lc, pass, tl, details);
 }
 
 hipError_t launch_encode_flow(int prec, Launch lc, uint32_t nblocks, int pass,
                               int tl, int cpt, double* details, hipStream_t s)
 {
     if (prec == HW_FP64) {
-        if (details)
-            hipLaunchKernelGGL((k_encode<double, 3, true, true>), dim3(nblocks),
-                               dim3(kBlock), 0, s, lc, pass, tl, cpt, details);
-        else
-            hipLaunchKernelGGL((k_encode<double, 3, true, false>), dim3(nblocks),
-                               dim3(kBlock), 0, s, lc, pass, tl, cpt, details);
+        if (details) encode_flow_t<double, true>(lc, nblocks, pass, tl, cpt, details, s);
+        else encode_flow_t<double, false>(lc, nblocks, pass, tl, cpt, details, s);
     } else {
-        if (details)
-            hipLaunchKernelGGL((k_encode<float, 3, true, true>), dim3(nblocks),
-                               dim3(kBlock), 0, s, lc, pass, tl, cpt, details);
-        else
-            hipLaunchKernelGGL((k_encode<float, 3, true, false>), dim3(nblocks),
-                               dim3(kBlock), 0, s, lc, pass, tl, cpt, details);
+        if (details) encode_flow_t<float, true>(lc, nblocks, pass, tl, cpt, details, s);
+        else encode_flow_t<float, false>(lc, nblocks, pass, tl, cpt, details, s);
     }
     return hipGetLastError();
 }
@@ -1533,7 +1584,7 @@ hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, hipStream_t 
 
 hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(n), dim3(kBlock), 0, s, descs,
+    hipLaunchKernelGGL(k_finalize, dim3(n), dim3(kFinalBlock), 0, s, descs,
                        (int)(grid + heavy_grid(grid)));
     return hipGetLastError();
 }
@@ -1545,6 +1596,24 @@ hipError_t launch_fv1(int prec, const Desc* descs, int n, uint32_t grid,
     if (e == hipSuccess) e = launch_fill(prec, fill, fill_blocks, s);
     if (e == hipSuccess) e = launch_finalize(descs, n, grid, s);
     return e;
+}
+
+// Clears the FV1 write history of one problem (every entry then names no
+// step, so the next two steps store everything).
+__global__ __launch_bounds__(kBlock) void k_forget(const Desc* dd)
+{
+    const gp<uint64_t> hist = glob(dd->hist);
+    const uint32_t n = dd->nhist;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        hist[i] = 0ull;
+}
+
+hipError_t launch_forget(const Desc* dd, uint64_t nhist, hipStream_t s)
+{
+    uint64_t blocks = (nhist + kBlock - 1) / kBlock;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_forget, dim3((uint32_t)blocks), dim3(kBlock), 0, s, dd);
+    return hipGetLastError();
 }
 
 hipError_t launch_export(int prec, const Desc* dd, uint64_t N, double* h,

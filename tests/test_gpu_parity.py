@@ -249,20 +249,27 @@ def test_fp32_bulk_error_against_fp64_oracle(hw):
 def test_batch_equals_individual_runs(hw):
     """Problems of different L and eps in one plan evolve exactly as when
     each runs alone."""
-    ws = [W.dambreak_bumps_l6(L=5, seed=21), W.circular_dambreak_l10(L=7),
-          W.dambreak_bumps_l6(L=3, seed=22), W.sheetflow_l13(L=6)]
+    ws = [W.dambreak_bumps_l6(L=5, seed=21), W.dambreak_bumps_l6(L=4, seed=23),
+          W.circular_dambreak_l10(L=7), W.dambreak_bumps_l6(L=3, seed=22),
+          W.sheetflow_l13(L=6)]
     ws[0].params = dict(ws[0].params, t_end=math.inf, eps=1e-2)
-    ws[2].params = dict(ws[2].params, t_end=math.inf, eps=1e-4)
+    ws[1].params = dict(ws[1].params, t_end=0.01)   # finishes after a few steps
+    ws[3].params = dict(ws[3].params, t_end=math.inf, eps=1e-4)
     steps = 25
     sims = [_sim(hw, w) for w in ws]
     plan = hw.Plan([s.problem for s in sims], [s.buffers for s in sims])
     stats = hw.hwfv1_run_batch(plan, steps)
-    for w, s, st in zip(ws, sims, stats):
+    for i, (w, s, st) in enumerate(zip(ws, sims, stats)):
         ref = _sim(hw, w)
         ref.run(steps)
         a, b = s.export(), ref.export()
         log("  batch", w.name, "steps", st["steps"])
-        assert st["steps"] == steps
+        if i == 1:
+            # reached t_end early; the other problems kept stepping
+            assert 0 < st["steps"] < steps and abs(s.scalars()["t"] - 0.01) <= 1e-15
+            assert st["steps"] == ref.scalars()["step"]
+        else:
+            assert st["steps"] == steps
         for x, y in zip(a, b):
             assert np.array_equal(x, y)
         assert np.array_equal(s.buffers.leaf_list(), ref.buffers.leaf_list())
@@ -291,6 +298,57 @@ def test_launch_shapes_do_not_change_results(hw, precision):
             for x, y in zip(ref, out):
                 assert np.array_equal(x, y)
         plan.close()
+
+
+def _flood_with_recession(L=8):
+    """Hydrograph case at small L whose inflow stops early: cells get wet,
+    and blocks stay dry, turn wet and settle while the run goes on."""
+    w = W.hydrograph_l12(L=L)
+    w.params = dict(w.params, t_peak=300.0, t_base=600.0, t_end=math.inf)
+    return w
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_write_history_does_not_change_results(hw, precision):
+    """The FV1 step skips the stores of blocks that stayed dry; forgetting
+    the history before every step (so that nothing is skipped) must give
+    the same states, bit for bit."""
+    w = _flood_with_recession()
+    a, b = _sim(hw, w, precision), _sim(hw, w, precision)
+    steps = 240
+    a.run(steps)
+    for _ in range(steps):
+        hw.hw_forget(b.problem, b.buffers, stream=b.stream)
+        b.run(1)
+    sa, sb = a.scalars(), b.scalars()
+    log("  history", precision, "t", sa["t"], "leaves", sa["n_leaves"],
+        "wet cells", int((a.export()[0] > w.params["h_tol"]).sum()))
+    assert sa["step"] == sb["step"] == steps and sa["t"] == sb["t"]
+    assert sa["mass"] == sb["mass"]
+    for x, y in zip(a.export(), b.export()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.buffers.leaf_list(), b.buffers.leaf_list())
+
+
+def test_forget_after_restoring_a_state(hw):
+    """A saved state written back into the buffers, followed by hw_forget,
+    continues exactly as the first time."""
+    w = _flood_with_recession()
+    sim = _sim(hw, w)
+    sim.run(60)
+    snap = ([t.clone() for t in sim.buffers.fine[0]], [t.clone() for t in sim.buffers.fine[1]],
+            sim.buffers.scal.clone())
+    sim.run(40)
+    ref = sim.export()
+    for dst, src in zip(sim.buffers.fine[0], snap[0]):
+        dst.copy_(src)
+    for dst, src in zip(sim.buffers.fine[1], snap[1]):
+        dst.copy_(src)
+    sim.buffers.scal.copy_(snap[2])
+    hw.hw_forget(sim.problem, sim.buffers, stream=sim.stream)
+    sim.run(40)
+    for x, y in zip(ref, sim.export()):
+        assert np.array_equal(x, y)
 
 
 def test_autotune_restores_state_and_picks_a_candidate(hw):
