@@ -486,17 +486,29 @@ __global__ __launch_bounds__(1024) void k_trav_scan(const Desc* descs)
 {
     __shared__ uint32_t lds[32];
     const Desc& d = descs[blockIdx.x];
-    if (d.scal->done) return;
+    const uint32_t done = glob(d.scal)->done;
+    const gp<uint32_t> cnt = glob(d.tcount);
+    const uint32_t n = d.ntrav;
+    // four consecutive counts per thread and round, loaded together
     uint32_t carry = 0;
-    for (uint32_t base = 0; base < d.ntrav; base += blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t v = i < d.ntrav ? d.tcount[i] : 0u;
+    for (uint32_t base = 0; base < n; base += 4 * blockDim.x) {
+        const uint32_t i0 = base + 4 * threadIdx.x;
+        uint32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = i0 + k < n ? cnt[i0 + k] : 0u;
+        const uint32_t sum = (v[0] + v[1]) + (v[2] + v[3]);
         uint32_t total;
-        const uint32_t excl = block_excl_scan(v, lds, total);
-        if (i < d.ntrav) d.tcount[i] = carry + excl;
+        uint32_t excl = carry + block_excl_scan(sum, lds, total);
+        if (!done) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (i0 + k < n) cnt[i0 + k] = excl;
+                excl += v[k];
+            }
+        }
         carry += total;
     }
-    if (threadIdx.x == 0) d.scal->n_leaves = carry;
+    if (threadIdx.x == 0 && !done) glob(d.scal)->n_leaves = carry;
 }
 
 // ---------------------------------------------------------------------------
@@ -791,17 +803,17 @@ __device__ inline void acc_flush(Acc& a, double (*red)[kPartial], double* rec)
         if (lane == 0) red[wid][q] = x;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    // one thread per slot combines the waves in ascending order
+    if (threadIdx.x < kPartial) {
+        const int q = threadIdx.x;
         const int nw = blockDim.x / kWave;
-        for (int q = 0; q < kPartial; ++q) {
-            double r = red[0][q];
-            for (int w = 1; w < nw; ++w) {
-                if (slot_is_sum(q)) r += red[w][q];
-                else r = red[w][q] > r ? red[w][q] : r;
-            }
-            if (slot_is_sum(q)) rec[q] += r;
-            else rec[q] = r > rec[q] ? r : rec[q];
+        const bool sum = slot_is_sum(q);
+        double r = red[0][q];
+        for (int w = 1; w < nw; ++w) {
+            const double y = red[w][q];
+            r = sum ? r + y : (y > r ? y : r);
         }
+        rec[q] = sum ? rec[q] + r : (r > rec[q] ? r : rec[q]);
     }
     __syncthreads();
     acc_reset(a);
@@ -1036,6 +1048,43 @@ __device__ inline void light_probe(const Fv1Ctx<T>& x, const uint32_t idx[kLeafB
     }
 }
 
+// light_probe for a problem whose leaves are all finest: leaf i is finest
+// cell i and every neighbour is a finest leaf, so no index, no leaf-level
+// byte and no coarser depth is needed; all depths come from one base.
+template <typename T>
+__device__ inline void light_probe_finest(const Fv1Ctx<T>& x, uint32_t base, LightBatch<T>& b)
+{
+    constexpr int U = kLeafBatch;
+    const int L = x.L;
+    const T tol = (T)x.h_tol;
+    const uint32_t lvmask = L > 0 ? (0xffffffffu >> (32 - 2 * L)) : 0u;
+    const uint32_t xm = 0x55555555u & lvmask, ym = 0xaaaaaaaau & lvmask;
+    T hh[U][5];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        uint32_t c = base + (uint32_t)u * kBlock + threadIdx.x;
+        c = c < x.nl ? c : x.nl - 1u;
+        b.m[u] = L;
+        b.c[u] = c;
+        const uint32_t w = (c & xm) != 0 ? morton_xm(c, xm, ym) : c;
+        const uint32_t e = (c & xm) != xm ? morton_xp(c, xm, ym) : c;
+        const uint32_t so = (c & ym) != 0 ? morton_ym(c, xm, ym) : c;
+        const uint32_t no = (c & ym) != ym ? morton_yp(c, xm, ym) : c;
+        hh[u][0] = ld_off(x.fin[0], c * (uint32_t)sizeof(T));
+        hh[u][1] = ld_off(x.fin[0], w * (uint32_t)sizeof(T));
+        hh[u][2] = ld_off(x.fin[0], e * (uint32_t)sizeof(T));
+        hh[u][3] = ld_off(x.fin[0], so * (uint32_t)sizeof(T));
+        hh[u][4] = ld_off(x.fin[0], no * (uint32_t)sizeof(T));
+        b.e[u] = x.hist[uniform(c) >> 6];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        b.h[u] = hh[u][0];
+        b.dry[u] = hh[u][0] <= tol && hh[u][1] <= tol && hh[u][2] <= tol &&
+                   hh[u][3] <= tol && hh[u][4] <= tol && !inflow_on<T>(x, L, b.c[u]);
+    }
+}
+
 // The dry shortcut's result (identical to the full update, see fv1_leaf);
 // the stores are left out when the set being written already holds it.
 template <typename T>
@@ -1089,7 +1138,24 @@ struct Fv1Sched {
     uint32_t c_begin, c_end, g8;
 };
 
-__device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre)
+// Whether every finest cell of the problem is a leaf this step (the leaf
+// list is then the identity on the finest level).
+__device__ inline bool all_finest(const Desc& d, uint64_t n_leaves)
+{
+    return n_leaves == (1ull << (2 * d.L));
+}
+
+// Problems taken by a kernel: every problem (kAllProblems), only those whose
+// leaves are all finest (kFinestOnly), or only the others (kMixedOnly).
+enum { kAllProblems = 0, kFinestOnly = 1, kMixedOnly = 2 };
+
+__device__ inline bool takes(int mode, const Desc& d, uint64_t nl)
+{
+    return mode == kAllProblems || (mode == kFinestOnly) == all_finest(d, nl);
+}
+
+__device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre,
+                                        int mode = kAllProblems)
 {
     constexpr uint32_t SC = kLeafBatch * kBlock;
     if (threadIdx.x == 0) {
@@ -1097,8 +1163,9 @@ __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre
         for (int s = 0; s < n; ++s) {
             cpre[s] = a;
             const hw_scalars* sc = descs[s].scal;
-            const uint32_t nl = sc->done ? 0u : (uint32_t)sc->n_leaves;
-            a += (nl + SC - 1) / SC;
+            const uint64_t nl = sc->n_leaves;
+            const bool mine = !sc->done && takes(mode, descs[s], nl);
+            a += mine ? ((uint32_t)nl + SC - 1) / SC : 0u;
         }
         cpre[n] = a;
     }
@@ -1117,7 +1184,7 @@ __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre
 // dry (no rain, no inflow on them) are finished here; the others are marked
 // in the wet table (one byte per super-chunk and wave, bit u for the wave's
 // u-th sub-chunk) for the heavy kernel.  Records go to slots [0, gridDim.x).
-template <typename T>
+template <typename T, bool FIN>
 __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ descs, int n)
 {
     constexpr int U = kLeafBatch;
@@ -1128,7 +1195,8 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
     const int tid = threadIdx.x;
     const int wid = tid / kWave;
     for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
-    const Fv1Sched f = fv1_schedule(descs, n, cpre);
+    const int mode = FIN ? kFinestOnly : kMixedOnly;
+    const Fv1Sched f = fv1_schedule(descs, n, cpre, mode);
     Acc acc;
     acc_reset(acc);
     int cs = -1;
@@ -1149,10 +1217,14 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
         }
         const uint32_t sc = ch - c0;
         const uint32_t base = sc * SC;
-        uint32_t idx[U];
-        light_indices<T>(x, base, idx);
         LightBatch<T> b;
-        light_probe<T>(x, idx, b);
+        if (FIN) {
+            light_probe_finest<T>(x, base, b);
+        } else {
+            uint32_t idx[U];
+            light_indices<T>(x, base, idx);
+            light_probe<T>(x, idx, b);
+        }
         uint32_t bits = 0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1166,10 +1238,13 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
     }
     if (cs >= 0) acc_flush(acc, red, rec[cs]);
     __syncthreads();
+    // records only for the problems this kernel takes (the other light
+    // kernel writes the same slots for the rest)
     for (int q = tid; q < n * kPartial; q += kBlock) {
         const int s = q / kPartial;
-        descs[s].partials[(uint64_t)blockIdx.x * kPartial + q % kPartial] =
-            rec[s][q % kPartial];
+        if (takes(mode, descs[s], descs[s].scal->n_leaves))
+            descs[s].partials[(uint64_t)blockIdx.x * kPartial + q % kPartial] =
+                rec[s][q % kPartial];
     }
 }
 
@@ -1235,11 +1310,14 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
             }
             const uint32_t mine = (wj >> (8 * wid)) & ((1u << kLeafBatch) - 1u);
             const uint32_t base = (ch - c0) * SC;
+            const bool finest = (uint64_t)x.nl == (1ull << (2 * x.L));
+            const uint32_t fin_off = (uint32_t)level_off(x.L);
 #pragma unroll 1
             for (int u = 0; u < kLeafBatch; ++u) {
                 if (!((mine >> u) & 1u)) continue;
                 const uint32_t leaf = base + (uint32_t)u * kBlock + tid;
-                if (leaf < x.nl) fv1_leaf<T>(x, x.leaves[leaf], acc);
+                if (leaf < x.nl)
+                    fv1_leaf<T>(x, finest ? fin_off + leaf : x.leaves[leaf], acc);
             }
         }
     }
@@ -1289,13 +1367,17 @@ __global__ __launch_bounds__(kFinalBlock) void k_finalize(const Desc* descs,
                                                           int fv1_grid)
 {
     __shared__ double red[kFinalBlock / kWave][kPartial];
+    __shared__ double tot[kPartial];
     const Desc& d = descs[blockIdx.x];
-    hw_scalars* sc = d.scal;
-    if (sc->done) return;
+    const gp<hw_scalars> sc = glob(d.scal);
+    // Every value this kernel reads is requested before any is used: the
+    // scalars, and the records (four per thread and round; a record past the
+    // end reads as zeros, the identity of every slot).  A finished problem
+    // still reads them and writes nothing.
+    const uint32_t done = sc->done;
+    const double t = sc->t, dt = sc->dt;
     Acc a;
     acc_reset(a);
-    // four records per thread and round, all loaded before any is combined
-    // (a record past the end reads as zeros, the identity of every slot)
     const gp<const vd2> pr = reinterpret_cast<gp<const vd2>>(glob(d.partials));
     for (int b0 = threadIdx.x; b0 < fv1_grid; b0 += 4 * blockDim.x) {
         vd2 r[4][kPartial / 2];
@@ -1318,12 +1400,11 @@ __global__ __launch_bounds__(kFinalBlock) void k_finalize(const Desc* descs,
             acc_add_record(a, v);
         }
     }
-    __shared__ double tot[kPartial];
     if (threadIdx.x < kPartial) tot[threadIdx.x] = 0.0;
     __syncthreads();
     acc_flush(a, red, tot);
-    if (threadIdx.x == 0) {
-        const double tn = sc->t + sc->dt;
+    if (threadIdx.x == 0 && !done) {
+        const double tn = t + dt;
         const double ms = tot[0];
         const double dmin = d.dx < d.dy ? d.dx : d.dy;
         double dtn;
@@ -1564,10 +1645,12 @@ hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
     (void)waves;
     const uint32_t gh = heavy_grid(grid);
     if (prec == HW_FP64) {
-        hipLaunchKernelGGL(k_fv1_light<double>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+        hipLaunchKernelGGL((k_fv1_light<double, true>), dim3(grid), dim3(kBlock), 0, s, descs, n);
+        hipLaunchKernelGGL((k_fv1_light<double, false>), dim3(grid), dim3(kBlock), 0, s, descs, n);
         hipLaunchKernelGGL(k_fv1_heavy<double>, dim3(gh), dim3(kBlock), 0, s, descs, n, grid);
     } else {
-        hipLaunchKernelGGL(k_fv1_light<float>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+        hipLaunchKernelGGL((k_fv1_light<float, true>), dim3(grid), dim3(kBlock), 0, s, descs, n);
+        hipLaunchKernelGGL((k_fv1_light<float, false>), dim3(grid), dim3(kBlock), 0, s, descs, n);
         hipLaunchKernelGGL(k_fv1_heavy<float>, dim3(gh), dim3(kBlock), 0, s, descs, n, grid);
     }
     return hipGetLastError();

@@ -263,7 +263,8 @@ def test_batch_equals_individual_runs(hw):
         ref = _sim(hw, w)
         ref.run(steps)
         a, b = s.export(), ref.export()
-        log("  batch", w.name, "steps", st["steps"])
+        log("  batch", w.name, "steps", st["steps"], "leaves", s.scalars()["n_leaves"],
+            "of", 4 ** w.L)
         if i == 1:
             # reached t_end early; the other problems kept stepping
             assert 0 < st["steps"] < steps and abs(s.scalars()["t"] - 0.01) <= 1e-15
