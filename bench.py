@@ -258,6 +258,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the no-write-skip and fully wet FP64 runs")
     ap.add_argument("--tuning", default=None, metavar="CPT,GRID",
                     help="fixed launch shape for the single-problem runs "
                          "(encode cells per thread, FV1 workgroups) instead of "
@@ -312,6 +314,38 @@ def main():
         "roofline": roofline(r64, L, 8, "fp64"),
         "tuning": r64["tuning"], "autotune_ms_per_step": r64["tuning_table"],
     }
+    if not args.no_variants:
+        # The same FP64 run with every leaf stored every step (no skip of
+        # unchanged dry blocks), for comparison with the default.
+        tu = dict(r64["tuning"], fv1_write_skip=0)
+        rns = time_single(hw, w, "fp64", args.steps, args.warmup, args.prof_steps, tu)
+        line["no_write_skip"] = {
+            "value": round(args.steps / (rns["ms"] * 1e-3), 2), "unit": "timesteps/s",
+            "ms_per_step": round(rns["ms"] / args.steps, 5),
+            "fv1_ms": round(rns["prof"]["fv1"], 5),
+            "roofline": roofline(rns, L, 8),
+            "note": "FP64, same workload and steps, fv1_write_skip=0",
+        }
+        rns["plan"].close()
+        rns["sim"].close()
+        del rns
+        # Every cell wet: every leaf takes the full FV1 update.
+        ww = W.flooded_basin_l12()
+        rw = time_single(hw, ww, "fp64", ww.n_steps, 5, args.prof_steps, tuning)
+        h_end = hw.hw_export(rw["sim"].problem, rw["sim"].buffers)[0]
+        line["fully_wet"] = {
+            "workload": ww.name, "steps": ww.n_steps,
+            "value": round(ww.n_steps / (rw["ms"] * 1e-3), 2), "unit": "timesteps/s",
+            "ms_per_step": round(rw["ms"] / ww.n_steps, 5),
+            "leaf_updates_per_s": rw["leaf_updates"] / (rw["ms"] * 1e-3),
+            "n_leaves": int(rw["scalars"]["n_leaves"]),
+            "wet_fraction": float((h_end > ww.params["h_tol"]).float().mean().item()),
+            "roofline": roofline(rw, L, 8),
+            "tuning": rw["tuning"],
+        }
+        rw["plan"].close()
+        rw["sim"].close()
+        del rw, h_end
     if not args.no_fp32:
         r32 = time_single(hw, w, "fp32_bulk", args.steps, args.warmup, args.prof_steps,
                           tuning)

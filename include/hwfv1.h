@@ -173,8 +173,10 @@ typedef struct hw_tuning {
     int32_t fv1_block;               /* reserved (FV1 workgroups are 256)  */
     int32_t fv1_grid;                /* FV1 persistent workgroups, 8..8192,
                                         0 = automatic                      */
-    int32_t fv1_min_waves;           /* FV1 occupancy request: 0 (compiler
-                                        choice), 5, 6 or 8 waves per SIMD  */
+    int32_t fv1_write_skip;          /* 1: skip the stores of 64-cell blocks
+                                        the dry case left unchanged at the
+                                        two previous steps (see hw_forget);
+                                        0: store every leaf every step     */
 } hw_tuning;
 
 typedef struct hw_plan hw_plan;

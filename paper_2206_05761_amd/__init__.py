@@ -67,7 +67,7 @@ class HwBuffers(C.Structure):
 class HwTuning(C.Structure):
     _fields_ = [("encode_cells_per_thread", C.c_int32),
                 ("fv1_block", C.c_int32), ("fv1_grid", C.c_int32),
-                ("fv1_min_waves", C.c_int32)]
+                ("fv1_write_skip", C.c_int32)]
 
 
 class HwStats(C.Structure):
@@ -310,7 +310,7 @@ class Plan:
             tu = HwTuning(int(tuning.get("encode_cells_per_thread", 0)),
                           int(tuning.get("fv1_block", 0)),
                           int(tuning.get("fv1_grid", 0)),
-                          int(tuning.get("fv1_min_waves", 0)))
+                          int(tuning.get("fv1_write_skip", 1)))
         h = C.c_void_p()
         _check(lib().hw_plan_create(C.byref(h), self._probs, self._bufs, n,
                                     C.byref(tu) if tu is not None else None))

@@ -201,6 +201,7 @@ Desc make_desc(const hw_problem* p, const hw_buffers* b, double* partials)
     d.precision = p->precision;
     for (int k = 0; k < 4; ++k) d.bc[k] = p->bc[k];
     d.group_level = group_level(p->L);
+    d.write_skip = 1;
     d.eps = p->eps;
     d.g = p->g;
     d.cfl = p->cfl;
@@ -287,7 +288,7 @@ struct hw_plan {
     int precision = 0;
     int tl = 5, cp = 1;
     uint32_t fv1_grid = 8;
-    int fv1_waves = 0;
+    int write_skip = 1;
     std::vector<hw_problem> problems;
     std::vector<hw_buffers> buffers;
     std::vector<Desc> host_desc;
@@ -334,7 +335,7 @@ hipError_t enqueue_phase(hw_plan* pl, int phase, hipStream_t s)
         break;
     case HW_PH_FV1:
         e = hw::launch_fv1_only(pl->precision, pl->d_desc, n, pl->fv1_grid,
-                                pl->fv1_waves, s);
+                                0, s);
         break;
     case HW_PH_FILL:
         e = hw::launch_fill(pl->precision, Launch{pl->d_desc, pl->trav_prefix, n},
@@ -480,7 +481,7 @@ void hw_default_tuning(const hw_problem* p, hw_tuning* out)
     out->encode_cells_per_thread = (fp32 && L >= 10) ? 16 : 4;
     out->fv1_block = hw::kBlock;
     out->fv1_grid = 0;
-    out->fv1_min_waves = 0;
+    out->fv1_write_skip = 1;
 }
 
 int hw_ingest(const hw_problem* p, const hw_buffers* b, const double* h,
@@ -638,15 +639,14 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
             return fail(HW_EINVAL, "fv1_grid must be in 0..%d", hw::kMaxFv1Grid);
         }
         tu.fv1_grid = tuning->fv1_grid;
-        if (tuning->fv1_min_waves != 0 && tuning->fv1_min_waves != 5 &&
-            tuning->fv1_min_waves != 6 && tuning->fv1_min_waves != 8) {
+        if (tuning->fv1_write_skip != 0 && tuning->fv1_write_skip != 1) {
             delete pl;
-            return fail(HW_EINVAL, "fv1_min_waves must be 0, 5, 6 or 8");
+            return fail(HW_EINVAL, "fv1_write_skip must be 0 or 1");
         }
-        tu.fv1_min_waves = tuning->fv1_min_waves;
+        tu.fv1_write_skip = tuning->fv1_write_skip;
     }
     pl->cp = tu.encode_cells_per_thread == 16 ? 2 : 1;
-    pl->fv1_waves = tu.fv1_min_waves;
+    pl->write_skip = tu.fv1_write_skip;
     pl->tl = pass_levels(pl->cp);
     pl->fv1_grid = tu.fv1_grid > 0 ? (uint32_t)((tu.fv1_grid + 7) / 8 * 8)
                                    : default_fv1_grid(max_leaves);
@@ -709,10 +709,12 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
     pl->d_desc = reinterpret_cast<Desc*>(base);
     uint32_t* d_pre = reinterpret_cast<uint32_t*>(base + desc_bytes);
     pl->d_partials = reinterpret_cast<double*>(base + desc_bytes + pre_bytes);
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         pl->host_desc.push_back(make_desc(
             &problems[i], &buffers[i],
             pl->d_partials + 2 * (size_t)i * pl->fv1_grid * hw::kPartial));
+        pl->host_desc.back().write_skip = pl->write_skip;
+    }
     const bool single = n == 1;
     for (int k = 0; k < pl->passes; ++k)
         pl->enc_prefix.push_back(single ? nullptr : d_pre + enc_off[k]);

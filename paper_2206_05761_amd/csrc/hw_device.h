@@ -21,7 +21,7 @@ constexpr int kLeafBatch = 4;           // leaves per FV1 thread per iteration
 struct Desc {
     int32_t L, precision, bc[4];
     int32_t group_level;   // level of the traversal groups (max(L-2, 0))
-    int32_t pad0;
+    int32_t write_skip;    // FV1 may skip stores of unchanged dry blocks
     double eps, g, cfl, h_tol, dx, dy, dt_max, manning_n, rain_rate;
     double inlet_y0, inlet_y1, q_peak, t_peak, t_base, t_end;
     void* fine[2][3];

@@ -533,6 +533,7 @@ struct Fv1Ctx {
     gp<const uint32_t> leaves;
     gp<uint64_t> hist;     // write history (light kernel)
     uint64_t step;         // index of the step being taken
+    int write_skip;        // stores of unchanged dry blocks may be skipped
     int L, Lg;
     int bc[4];
     double dx, dy, g, h_tol, manning_n, rain_rate;
@@ -568,6 +569,7 @@ __device__ inline void make_ctx(Fv1Ctx<T>& x, const Desc& d)
     x.leaves = glob(static_cast<const uint32_t*>(d.leaves));
     x.hist = glob(d.hist);
     x.step = sc->step;
+    x.write_skip = d.write_skip;
     x.L = d.L;
     x.Lg = d.group_level;
     for (int k = 0; k < 4; ++k) x.bc[k] = d.bc[k];
@@ -1121,7 +1123,7 @@ __device__ inline bool light_history(const Fv1Ctx<T>& x, bool ok, int m, uint32_
     const uint32_t c0 = uniform(c);
     const uint32_t c63 = (uint32_t)__builtin_amdgcn_readlane((int)c, kWave - 1);
     const bool block = !wave_any(!ok || m != x.L) && (c0 & 63u) == 0u && c63 == c0 + 63u;
-    if (!block) return false;
+    if (!block || !x.write_skip) return false;
     const bool valid = (e >> 2) == x.step;
     const uint64_t bits = ((valid ? (e << 1) : 0ull) | (dry ? 1ull : 0ull)) & 3ull;
     if ((threadIdx.x & (kWave - 1)) == 0) x.hist[c0 >> 6] = ((x.step + 1) << 2) | bits;

@@ -280,14 +280,14 @@ def test_batch_equals_individual_runs(hw):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
 def test_launch_shapes_do_not_change_results(hw, precision):
-    """Every encode tile size, FV1 grid and FV1 occupancy variant gives the
+    """Every encode tile size, FV1 grid and the FV1 store skip give the
     same state, bit for bit (the launch shape only reorders independent
     work; the mass sum may differ in the last bits)."""
     w = W.circular_dambreak_l10(L=9)
     ref = None
-    for tu in ({}, dict(encode_cells_per_thread=16, fv1_grid=8, fv1_min_waves=8),
-               dict(encode_cells_per_thread=4, fv1_grid=4096, fv1_min_waves=5),
-               dict(encode_cells_per_thread=16, fv1_grid=512, fv1_min_waves=6)):
+    for tu in ({}, dict(encode_cells_per_thread=16, fv1_grid=8),
+               dict(encode_cells_per_thread=4, fv1_grid=4096, fv1_write_skip=0),
+               dict(encode_cells_per_thread=16, fv1_grid=512)):
         sim = _sim(hw, w, precision)
         plan = hw.Plan([sim.problem], [sim.buffers], tuning=tu)
         hw.hwfv1_run(sim.problem, sim.buffers, 30, plan=plan)

@@ -149,6 +149,23 @@ def hydrograph_l12(seed: int = 3, L: int = 12, n_steps: int = 2000,
                     n_steps=n_steps, meta=dict(seed=seed))
 
 
+def flooded_basin_l12(seed: int = 3, L: int = 12, n_steps: int = 200,
+                      relief: float = 50.0) -> Workload:
+    """The hydrograph terrain under still water 10 m above its highest point,
+    with a 2 m higher circular mound (radius 500 m) at the centre released
+    at t = 0: every cell is wet, so every leaf takes the full update."""
+    length = 10_000.0
+    p = base_params(L, length, 1e-3, manning_n=0.035, bc=("open",) * 4)
+    z = fractal_bed(L, relief, seed)
+    x, y = cell_centres(L, length)
+    r = np.sqrt((x - 5000.0) ** 2 + (y - 5000.0) ** 2)
+    eta = relief + 10.0 + np.where(r < 500.0, 2.0, 0.0)
+    h = eta - z
+    zero = np.zeros_like(h)
+    return Workload(f"flooded_basin_l{L}", p, h, zero, zero.copy(), z,
+                    n_steps=n_steps, meta=dict(seed=seed))
+
+
 def sheetflow_l13(seed: int = 5, L: int = 13, n_steps: int = 1000) -> Workload:
     length = 10_000.0
     p = base_params(L, length, 1e-4, manning_n=0.05, bc=("open",) * 4,
