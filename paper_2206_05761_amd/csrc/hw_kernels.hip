@@ -671,10 +671,11 @@ __device__ inline void store_run(gp<T> p, uint32_t cnt, T v)
     }
 }
 
+// 1/h for a wet depth, 0 for a dry one (velocities are then 0).
 template <typename T>
-__device__ inline T velocity(T h, T q, T tol)
+__device__ inline T inv_depth(T h, T tol)
 {
-    return h > tol ? q / h : T(0);
+    return h > tol ? T(1) / h : T(0);
 }
 
 // One face between a left and a right state (normal velocity un, tangential
@@ -734,11 +735,12 @@ __device__ inline void face_flux(T hl, T unl, T utl, double zl, T hr, T unr,
         F[1] = Fr[1];
         F[2] = Fr[2];
     } else {
+        // one reciprocal of the speed difference serves the three components
         const T slsr = sl * sr;
-        const T den = sr - sl;
+        const T inv = T(1) / (sr - sl);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            F[k] = ((sr * Fl[k] - sl * Fr[k]) + slsr * (Ur[k] - Ul[k])) / den;
+            F[k] = ((sr * Fl[k] - sl * Fr[k]) + slsr * (Ur[k] - Ul[k])) * inv;
     }
 }
 
@@ -751,13 +753,14 @@ __device__ inline double inflow_rate(const Fv1Ctx<T>& x, double t)
     return 0.0;
 }
 
+// Largest wave speed |u| + c of a cell; ih is 1/h (any value when dry).
 template <typename T>
-__device__ inline double wave_speed(T h, T qx, T qy, T g, T tol)
+__device__ inline double wave_speed(T h, T qx, T qy, T ih, T g, T tol)
 {
     if (!(h > tol)) return 0.0;
     const T c = sqrt(g * h);
-    const T u = qx / h;
-    const T v = qy / h;
+    const T u = qx * ih;
+    const T v = qy * ih;
     const T su = fabs(u) + c;
     const T sv = fabs(v) + c;
     return (double)(su > sv ? su : sv);
@@ -867,16 +870,19 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
     T us = T(0), vs = T(0), un = T(0), vn = T(0);
     const bool wet = own.h > tol || w.h > tol || e.h > tol || so.h > tol || no.h > tol;
     if (wave_any(wet)) {
-        uc = velocity(own.h, own.qx, tol);
-        vc = velocity(own.h, own.qy, tol);
-        uw = velocity(w.h, w.qx, tol);
-        vw = velocity(w.h, w.qy, tol);
-        ue = velocity(e.h, e.qx, tol);
-        ve = velocity(e.h, e.qy, tol);
-        us = velocity(so.h, so.qx, tol);
-        vs = velocity(so.h, so.qy, tol);
-        un = velocity(no.h, no.qx, tol);
-        vn = velocity(no.h, no.qy, tol);
+        const T rc = inv_depth(own.h, tol), rw = inv_depth(w.h, tol);
+        const T re = inv_depth(e.h, tol), rs = inv_depth(so.h, tol);
+        const T rn = inv_depth(no.h, tol);
+        uc = own.qx * rc;
+        vc = own.qy * rc;
+        uw = w.qx * rw;
+        vw = w.qy * rw;
+        ue = e.qx * re;
+        ve = e.qy * re;
+        us = so.qx * rs;
+        vs = so.qy * rs;
+        un = no.qx * rn;
+        vn = no.qy * rn;
     }
 
     T FE[3], FW[3], GN[3], GS[3];
@@ -918,16 +924,17 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
         h = T(0);
         acc.v[5] += 1.0;
     }
+    const T ih = inv_depth(h, tol);
     if (h <= tol) {
         qx = T(0);
         qy = T(0);
     } else if (x.manning_n > 0.0) {
         const T nm = (T)x.manning_n;
-        const T speed = sqrt(qx * qx + qy * qy) / h;
+        const T speed = sqrt(qx * qx + qy * qy) * ih;
         const T cf = g * nm * nm / cbrt(h);
-        const T den = T(1) + (T)dt * cf * speed / h;
-        qx = qx / den;
-        qy = qy / den;
+        const T iden = T(1) / (T(1) + (T)dt * cf * speed * ih);
+        qx = qx * iden;
+        qy = qy * iden;
     }
 
     // write-back: every finest descendant of the leaf in the other set,
@@ -937,7 +944,7 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
     store_run<T>(x.fout[1] + f0, cnt, qx);
     store_run<T>(x.fout[2] + f0, cnt, qy);
 
-    acc_max(acc, 0, wave_speed<T>(h, qx, qy, g, tol));
+    acc_max(acc, 0, wave_speed<T>(h, qx, qy, ih, g, tol));
     acc_max(acc, 1, fabs((double)h));
     acc_max(acc, 2, fabs((double)qx));
     acc_max(acc, 3, fabs((double)qy));
@@ -998,6 +1005,18 @@ __device__ inline void light_indices(const Fv1Ctx<T>& x, uint32_t base, uint32_t
     }
 }
 
+// Same-level neighbour codes of cell c on level m (the cell itself beyond
+// the domain edge), in the order W, E, S, N.
+__device__ inline void neighbour_codes(uint32_t c, int m, uint32_t nb[4])
+{
+    const uint32_t lvmask = m > 0 ? (0xffffffffu >> (32 - 2 * m)) : 0u;
+    const uint32_t xm = 0x55555555u & lvmask, ym = 0xaaaaaaaau & lvmask;
+    nb[0] = (c & xm) != 0 ? morton_xm(c, xm, ym) : c;
+    nb[1] = (c & xm) != xm ? morton_xp(c, xm, ym) : c;
+    nb[2] = (c & ym) != 0 ? morton_ym(c, xm, ym) : c;
+    nb[3] = (c & ym) != ym ? morton_yp(c, xm, ym) : c;
+}
+
 template <typename T>
 __device__ inline void light_probe(const Fv1Ctx<T>& x, const uint32_t idx[kLeafBatch],
                                    LightBatch<T>& b)
@@ -1005,7 +1024,6 @@ __device__ inline void light_probe(const Fv1Ctx<T>& x, const uint32_t idx[kLeafB
     constexpr int U = kLeafBatch;
     const int L = x.L;
     const T tol = (T)x.h_tol;
-    uint32_t nb[U][4];
     int lv[U][4];
     T hh[U][5];
 #pragma unroll
@@ -1014,18 +1032,14 @@ __device__ inline void light_probe(const Fv1Ctx<T>& x, const uint32_t idx[kLeafB
         const uint32_t c = idx[u] - (uint32_t)level_off(m);
         b.m[u] = m;
         b.c[u] = c;
-        const uint32_t lvmask = m > 0 ? (0xffffffffu >> (32 - 2 * m)) : 0u;
-        const uint32_t xm = 0x55555555u & lvmask, ym = 0xaaaaaaaau & lvmask;
-        nb[u][0] = (c & xm) != 0 ? morton_xm(c, xm, ym) : c;
-        nb[u][1] = (c & xm) != xm ? morton_xp(c, xm, ym) : c;
-        nb[u][2] = (c & ym) != 0 ? morton_ym(c, xm, ym) : c;
-        nb[u][3] = (c & ym) != ym ? morton_yp(c, xm, ym) : c;
+        uint32_t nb[4];
+        neighbour_codes(c, m, nb);
         const int sh = 2 * (L - m);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) lv[u][k] = ld_off(x.lmap, nb[u][k] << sh);
+        for (int k = 0; k < 4; ++k) lv[u][k] = ld_off(x.lmap, nb[k] << sh);
         hh[u][0] = *h_ptr<T>(x, m, c);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) hh[u][k + 1] = *h_ptr<T>(x, m, nb[u][k]);
+        for (int k = 0; k < 4; ++k) hh[u][k + 1] = *h_ptr<T>(x, m, nb[k]);
         // c < 4^m <= 4^L, so c / 64 indexes the table even when unused
         b.e[u] = x.hist[uniform(c) >> 6];
     }
@@ -1035,12 +1049,16 @@ __device__ inline void light_probe(const Fv1Ctx<T>& x, const uint32_t idx[kLeafB
 #pragma unroll
         for (int k = 0; k < 4; ++k) coarser = coarser || lv[u][k] < b.m[u];
     if (wave_any(coarser)) {
+        // rare: some neighbour is a coarser leaf; its codes are recomputed
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+            uint32_t nb[4];
+            neighbour_codes(b.c[u], b.m[u], nb);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (lv[u][k] < b.m[u])
-                    hh[u][k + 1] = *h_ptr<T>(x, lv[u][k], nb[u][k] >> (2 * (b.m[u] - lv[u][k])));
+                    hh[u][k + 1] = *h_ptr<T>(x, lv[u][k], nb[k] >> (2 * (b.m[u] - lv[u][k])));
+        }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1471,7 +1489,7 @@ __global__ __launch_bounds__(kBlock) void k_ingest(const Desc* dd,
         fqx[f] = tx;
         fqy[f] = ty;
         zl[f] = zv;
-        acc_max(a, 0, wave_speed<T>(th, tx, ty, g, tol));
+        acc_max(a, 0, wave_speed<T>(th, tx, ty, inv_depth(th, (T)tol), g, tol));
         acc_max(a, 1, fabs((double)th));
         acc_max(a, 2, fabs((double)tx));
         acc_max(a, 3, fabs((double)ty));
@@ -1634,10 +1652,10 @@ hipError_t launch_traverse(Launch lc, uint32_t nblocks, hipStream_t s)
 }
 
 // Workgroups of the heavy FV1 kernel: about as many as are resident at its
-// occupancy (two waves per SIMD), never more than the light kernel's.
+// occupancy (three waves per SIMD), never more than the light kernel's.
 uint32_t heavy_grid(uint32_t grid)
 {
-    constexpr uint32_t kHeavy = 512;
+    constexpr uint32_t kHeavy = 768;
     return grid < kHeavy ? grid : kHeavy;
 }
 

@@ -72,7 +72,27 @@ def test_ingest_matches_oracle(hw, L):
 # ----------------------------------------------------------------------------
 # phase by phase against the oracle's phases
 # ----------------------------------------------------------------------------
+def _load_oracle_state(hw, sim, o, z):
+    """Put the oracle's current state (fields, t, dt, step) into the GPU
+    buffers, so that the next phases start from identical inputs."""
+    import torch
+    ho, qxo, qyo = o.fine()
+    dev = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1), device="cuda")
+           for a in (ho, qxo, qyo, z)]
+    hw.hw_ingest(sim.problem, sim.buffers, *dev)
+    torch.cuda.synchronize()
+    so = o.scalars()
+    sc = hw.HwScalars.from_buffer_copy(sim.buffers.scal.cpu().numpy().tobytes())
+    sc.t, sc.dt, sc.step = so["t"], so["dt"], int(so["step"])
+    sim.buffers.scal.copy_(torch.frombuffer(bytearray(bytes(sc)), dtype=torch.uint8))
+    torch.cuda.synchronize()
+
+
 def _phase_case(hw, w, steps):
+    """Each step starts both sides from the oracle's state: encoding, flags,
+    regularisation and the leaf list must then agree exactly, the FV1 update
+    within the FP64 bar (the GPU takes one reciprocal where the definition
+    divides several times)."""
     import torch
     sim = _sim(hw, w)
     o = O.Oracle(w.params, w.h, w.qx, w.qy, w.z)
@@ -82,6 +102,8 @@ def _phase_case(hw, w, steps):
     det = torch.zeros(9 * max(nc, 1), dtype=torch.float64, device="cuda")
     for k in range(steps):
         log(w.name, "phase step", k)
+        if k > 0:
+            _load_oracle_state(hw, sim, o, w.z)
         hw.mra_encode(p, b, det)
         o.phase_encode()
         torch.cuda.synchronize()
