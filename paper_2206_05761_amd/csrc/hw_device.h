@@ -14,7 +14,7 @@ constexpr uint32_t kNone = 0xffffffffu; // "no coarse leaf" marker
 constexpr int kPartial = 8;             // doubles per FV1 partial record
 constexpr int kMaxScen = 64;            // problems per batch
 constexpr int kMaxFv1Grid = 8192;
-constexpr int kLeafBatch = 4;           // leaves per FV1 thread per iteration
+constexpr int kLeafBatch = 2;           // leaves per FV1 thread per iteration
 
 // Everything a kernel needs to know about one problem.  Lives in device
 // memory (the workspace for single-problem calls, the plan for batches).

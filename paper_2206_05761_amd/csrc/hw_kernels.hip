@@ -1134,6 +1134,19 @@ __device__ inline void fv1_dry_write(const Fv1Ctx<T>& x, int m, uint32_t c, T h,
 // other writer of B's cells (full update, coarser leaves, a misaligned
 // wave) does not refresh the entry, so its step no longer matches and the
 // next steps store again.  Returns true when the stores may be skipped.
+// The entry update and skip decision once the wave is known to be one
+// aligned block (c: a lane's cell; the block is c / 64).
+template <typename T>
+__device__ inline bool light_history_block(const Fv1Ctx<T>& x, bool block, uint32_t c,
+                                           bool dry, uint64_t e)
+{
+    if (!block || !x.write_skip) return false;
+    const bool valid = (e >> 2) == x.step;
+    const uint64_t bits = ((valid ? (e << 1) : 0ull) | (dry ? 1ull : 0ull)) & 3ull;
+    if ((threadIdx.x & (kWave - 1)) == 0) x.hist[c >> 6] = ((x.step + 1) << 2) | bits;
+    return dry && valid && (e & 3ull) == 3ull;
+}
+
 template <typename T>
 __device__ inline bool light_history(const Fv1Ctx<T>& x, bool ok, int m, uint32_t c,
                                      bool dry, uint64_t e)
@@ -1141,11 +1154,7 @@ __device__ inline bool light_history(const Fv1Ctx<T>& x, bool ok, int m, uint32_
     const uint32_t c0 = uniform(c);
     const uint32_t c63 = (uint32_t)__builtin_amdgcn_readlane((int)c, kWave - 1);
     const bool block = !wave_any(!ok || m != x.L) && (c0 & 63u) == 0u && c63 == c0 + 63u;
-    if (!block || !x.write_skip) return false;
-    const bool valid = (e >> 2) == x.step;
-    const uint64_t bits = ((valid ? (e << 1) : 0ull) | (dry ? 1ull : 0ull)) & 3ull;
-    if ((threadIdx.x & (kWave - 1)) == 0) x.hist[c0 >> 6] = ((x.step + 1) << 2) | bits;
-    return dry && valid && (e & 3ull) == 3ull;
+    return light_history_block<T>(x, block, c0, dry, e);
 }
 
 // Chunk bookkeeping shared by the two FV1 kernels: the leaves of every
@@ -1175,7 +1184,7 @@ __device__ inline bool takes(int mode, const Desc& d, uint64_t nl)
 }
 
 __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre,
-                                        int mode = kAllProblems)
+                                        int mode = kAllProblems, uint8_t* mine = nullptr)
 {
     constexpr uint32_t SC = kLeafBatch * kBlock;
     if (threadIdx.x == 0) {
@@ -1184,8 +1193,9 @@ __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre
             cpre[s] = a;
             const hw_scalars* sc = descs[s].scal;
             const uint64_t nl = sc->n_leaves;
-            const bool mine = !sc->done && takes(mode, descs[s], nl);
-            a += mine ? ((uint32_t)nl + SC - 1) / SC : 0u;
+            const bool m = !sc->done && takes(mode, descs[s], nl);
+            if (mine) mine[s] = m ? 1 : 0;
+            a += m ? ((uint32_t)nl + SC - 1) / SC : 0u;
         }
         cpre[n] = a;
     }
@@ -1215,8 +1225,12 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
     const int tid = threadIdx.x;
     const int wid = tid / kWave;
     for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
+    __shared__ uint8_t mine[kMaxScen];
     const int mode = FIN ? kFinestOnly : kMixedOnly;
-    const Fv1Sched f = fv1_schedule(descs, n, cpre, mode);
+    const Fv1Sched f = fv1_schedule(descs, n, cpre, mode, mine);
+    // no problem of this kind this step: nothing to update and no records
+    // to write (finalize reads records of problems that are stepping only)
+    if (uniform(cpre[n]) == 0u) return;
     Acc acc;
     acc_reset(acc);
     int cs = -1;
@@ -1238,21 +1252,40 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
         const uint32_t sc = ch - c0;
         const uint32_t base = sc * SC;
         LightBatch<T> b;
+        uint32_t bits = 0;
         if (FIN) {
             light_probe_finest<T>(x, base, b);
+            // every full wave is one aligned 64-cell block of finest leaves
+            const double area = x.dx * x.dy;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = base + (uint32_t)u * kBlock + tid < x.nl;
+                const bool wet = x.rain_rate != 0.0 || wave_any(ok && !b.dry[u]);
+                const bool skip = light_history_block<T>(x, !wave_any(!ok), b.c[u], !wet, b.e[u]);
+                if (wet) {
+                    bits |= 1u << u;
+                } else if (ok) {
+                    if (!skip) {
+                        x.fout[0][b.c[u]] = b.h[u];
+                        x.fout[1][b.c[u]] = T(0);
+                        x.fout[2][b.c[u]] = T(0);
+                    }
+                    acc_max(acc, 1, fabs((double)b.h[u]));
+                    acc.v[4] += (double)b.h[u] * area;
+                }
+            }
         } else {
             uint32_t idx[U];
             light_indices<T>(x, base, idx);
             light_probe<T>(x, idx, b);
-        }
-        uint32_t bits = 0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool ok = base + (uint32_t)u * kBlock + tid < x.nl;
-            const bool wet = x.rain_rate != 0.0 || wave_any(ok && !b.dry[u]);
-            const bool skip = light_history<T>(x, ok, b.m[u], b.c[u], !wet, b.e[u]);
-            if (wet) bits |= 1u << u;
-            else if (ok) fv1_dry_write<T>(x, b.m[u], b.c[u], b.h[u], acc, !skip);
+            for (int u = 0; u < U; ++u) {
+                const bool ok = base + (uint32_t)u * kBlock + tid < x.nl;
+                const bool wet = x.rain_rate != 0.0 || wave_any(ok && !b.dry[u]);
+                const bool skip = light_history<T>(x, ok, b.m[u], b.c[u], !wet, b.e[u]);
+                if (wet) bits |= 1u << u;
+                else if (ok) fv1_dry_write<T>(x, b.m[u], b.c[u], b.h[u], acc, !skip);
+            }
         }
         if ((tid & (kWave - 1)) == 0) wetb[4ull * sc + wid] = (uint8_t)bits;
     }
@@ -1262,7 +1295,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
     // kernel writes the same slots for the rest)
     for (int q = tid; q < n * kPartial; q += kBlock) {
         const int s = q / kPartial;
-        if (takes(mode, descs[s], descs[s].scal->n_leaves))
+        if (mine[s])
             descs[s].partials[(uint64_t)blockIdx.x * kPartial + q % kPartial] =
                 rec[s][q % kPartial];
     }
@@ -1328,14 +1361,26 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
                 c0 = uniform(cpre[s]);
                 c1 = uniform(cpre[s + 1]);
             }
-            const uint32_t mine = (wj >> (8 * wid)) & ((1u << kLeafBatch) - 1u);
+            // The marked sub-chunks of this super-chunk (bit u of byte w: the
+            // 64 leaves base + u kBlock + w kWave + lane) are dealt to the
+            // workgroup's waves in turn, whichever wave's position they hold.
             const uint32_t base = (ch - c0) * SC;
             const bool finest = (uint64_t)x.nl == (1ull << (2 * x.L));
             const uint32_t fin_off = (uint32_t)level_off(x.L);
+            const uint32_t lane_mask = (1u << kLeafBatch) - 1u;
+            uint32_t items = 0;   // bit 4 w + u
+#pragma unroll
+            for (int w = 0; w < kBlock / kWave; ++w)
+                items |= ((wj >> (8 * w)) & lane_mask) << (kLeafBatch * w);
+            items = uniform(items);
+            int k = 0;
 #pragma unroll 1
-            for (int u = 0; u < kLeafBatch; ++u) {
-                if (!((mine >> u) & 1u)) continue;
-                const uint32_t leaf = base + (uint32_t)u * kBlock + tid;
+            while (items) {
+                const int bit = __builtin_ctz(items);
+                items &= items - 1u;
+                if ((k++ & (kBlock / kWave - 1)) != wid) continue;
+                const uint32_t w = (uint32_t)bit / kLeafBatch, u = (uint32_t)bit % kLeafBatch;
+                const uint32_t leaf = base + u * kBlock + w * kWave + (uint32_t)lane;
                 if (leaf < x.nl)
                     fv1_leaf<T>(x, finest ? fin_off + leaf : x.leaves[leaf], acc);
             }
