@@ -140,7 +140,11 @@ typedef struct hw_scalars {
  *   fine[2][3]  two sets of finest h, qx, qy, N entries each, flow type;
  *               hw_scalars.cur names the set holding the current state and
  *               fv1_step writes the other one and flips cur
- *   coarse[3]   levels 0..L-1 of h, qx, qy, (N-1)/3 entries, flow type
+ *   coarse[3]   levels 0..L-1 of h, qx, qy, (N-1)/3 entries, flow type;
+ *               mra_encode writes every level, the time loop (hwfv1_run,
+ *               hwfv1_run_batch, hw_plan_profile) levels 0..L-2 only: the
+ *               step reads a level L-1 value from its four finest children
+ *               (the same value bit for bit)
  *   zhier       bed on levels 0..L, (4N-1)/3 FP64 (static after ingest)
  *   zsig        static bed significance flags, (N-1)/3 bytes
  *   raw         significance of the current step before regularisation

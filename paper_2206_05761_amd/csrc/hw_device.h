@@ -41,6 +41,8 @@ struct Desc {
     double* partials;      // FV1 / ingest partial records, kPartial each
     uint32_t ntrav;        // traversal workgroups of this problem
     uint32_t nhist;        // entries of hist
+    int32_t keep_parents;  // store level L-1 of h, qx, qy when encoding
+    int32_t pad1;
 };
 
 // Work decomposition of one launch: problem s owns workgroups

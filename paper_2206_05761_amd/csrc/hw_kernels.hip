@@ -136,18 +136,22 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     const gp<const uint8_t> zsig = glob(static_cast<const uint8_t*>(d.zsig));
     const gp<double> det = glob(details);
     const double eps = d.eps;
+    // Level L-1 of the flow variables is stored only when asked for (the
+    // time loop reads it from the finest level instead, see parent_value).
+    const bool keep_parents = d.keep_parents != 0;
 
     auto dst_of = [&](int v, int n) -> gp<T> { return dstb[v] + level_off(n); };
 
-    // Encode one cell (n, k) from its four children, store it, flag it.
-    auto emit = [&](int n, uint64_t k, const double (*ch)[4], double* out) {
+    // Encode one cell (n, k) from its four children, store it, flag it
+    // (zb: the cell's static bed flag, read ahead of time).
+    auto emit = [&](int n, uint64_t k, const double (*ch)[4], double* out, uint8_t zb) {
         const double thr = ldexp(eps, n - L);
         bool f = false;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             Haar hh = haar(ch[v][0], ch[v][1], ch[v][2], ch[v][3]);
             T sv = (T)hh.s;
-            dst_of(v, n)[k] = sv;
+            if (!FLOW || n != L - 1 || keep_parents) dst_of(v, n)[k] = sv;
             out[v] = (double)sv;
             if (significant(hh, smax[v], thr)) f = true;
             if (DET) {
@@ -159,12 +163,38 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
         }
         const uint64_t o = level_off(n) + k;
         uint8_t fl = f ? 1 : 0;
-        if (FLOW) fl |= zsig[o];
+        if (FLOW) fl |= zb;
         flags[o] = fl ? 1 : 0;
     };
 
     const int n_mid = n_in - cp;                  // level held per thread
     const uint32_t M = 1u << (2 * (lv - cp));     // active threads
+
+    // The static bed flags of every cell this thread will emit, requested
+    // together with the child values (one round trip instead of one per
+    // level).  Tail level i is n_mid - 1 - i, with M >> 2(i+1) threads.
+    constexpr int kTail = 6;
+    uint8_t zr[4] = {0, 0, 0, 0}, zr2 = 0, zt[kTail];
+    if (FLOW) {
+        if ((uint32_t)tid < M) {
+            const uint64_t o1 = level_off(n_in - 1) + ((uint64_t)b << (2 * (lv - 1)));
+            if (CP == 1 || cp == 1) {
+                zr[0] = zsig[o1 + tid];
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) zr[qq] = zsig[o1 + 4ull * tid + qq];
+                zr2 = zsig[level_off(n_in - 2) + ((uint64_t)b << (2 * (lv - 2))) + tid];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kTail; ++i) {
+            const int n = n_mid - 1 - i;
+            const uint32_t c = M >> (2 * (i + 1));
+            zt[i] = (n >= n_lo && (uint32_t)tid < c) ? zsig[level_off(n) + (uint64_t)b * c + tid]
+                                                      : (uint8_t)0;
+        }
+    }
+
     double p[NV];
     if ((uint32_t)tid < M) {
         const uint64_t tile_in = (uint64_t)b << (2 * lv);
@@ -179,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
 #pragma unroll
                     for (int q = 0; q < 4; ++q) ch[v][q] = (double)src[v][base + q];
             }
-            emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + tid, ch, p);
+            emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + tid, ch, p, zr[0]);
         } else {
             const uint64_t base = tile_in + 16ull * tid;
             double ch[4][NV][4];
@@ -198,11 +228,11 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
             for (int qq = 0; qq < 4; ++qq) {
                 double o[NV];
                 emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + 4ull * tid + qq,
-                     ch[qq], o);
+                     ch[qq], o, zr[qq]);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) mid[v][qq] = o[v];
             }
-            emit(n_in - 2, ((uint64_t)b << (2 * (lv - 2))) + tid, mid, p);
+            emit(n_in - 2, ((uint64_t)b << (2 * (lv - 2))) + tid, mid, p, zr2);
         }
     }
 
@@ -215,7 +245,10 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     __syncthreads();
     int pp = 0;
     uint32_t cnt = M;
-    for (int n = n_mid - 1; n >= n_lo; --n) {
+#pragma unroll
+    for (int i = 0; i < kTail; ++i) {
+        const int n = n_mid - 1 - i;
+        if (n < n_lo) break;
         cnt >>= 2;
         if ((uint32_t)tid < cnt) {
             double ch[NV][4];
@@ -223,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
             for (int v = 0; v < NV; ++v)
                 for (int q = 0; q < 4; ++q) ch[v][q] = lds[pp][v][4 * tid + q];
             double o[NV];
-            emit(n, (uint64_t)b * cnt + tid, ch, o);
+            emit(n, (uint64_t)b * cnt + tid, ch, o, zt[i]);
 #pragma unroll
             for (int v = 0; v < NV; ++v) lds[pp ^ 1][v][tid] = o[v];
         }
@@ -589,20 +622,37 @@ __device__ inline void make_ctx(Fv1Ctx<T>& x, const Desc& d)
     x.nl = uniform((uint32_t)sc->n_leaves);
 }
 
+// Value of the level-(L-1) cell k of one variable from its four finest
+// children, with the encoder's operations in the encoder's order (Eq. 3a
+// as in haar), so it equals the encoded value bit for bit.  The time loop
+// does not store level L-1; every reader takes it from here.
+template <typename T>
+__device__ inline T parent_value(gp<const T> f, uint32_t k)
+{
+    double c[4];
+    load4(f + 4ull * k, c);
+    const double a = c[0] + c[2];
+    const double b = c[1] + c[3];
+    return (T)(0.25 * (a + b));
+}
+
+// One variable of the hierarchy cell (n, k): finest set, parent rule or
+// coarse levels.
+template <typename T>
+__device__ inline T load_var(const Fv1Ctx<T>& x, int v, int n, uint32_t k)
+{
+    if (n == x.L) return x.fin[v][k];
+    if (n == x.L - 1) return parent_value<T>(x.fin[v], k);
+    return x.crs[v][level_off(n) + k];
+}
+
 template <typename T>
 __device__ inline Cell<T> load_cell(const Fv1Ctx<T>& x, int n, uint32_t k)
 {
     Cell<T> c;
-    if (n == x.L) {
-        c.h = x.fin[0][k];
-        c.qx = x.fin[1][k];
-        c.qy = x.fin[2][k];
-    } else {
-        const uint64_t o = level_off(n) + k;
-        c.h = x.crs[0][o];
-        c.qx = x.crs[1][o];
-        c.qy = x.crs[2][o];
-    }
+    c.h = load_var<T>(x, 0, n, k);
+    c.qx = load_var<T>(x, 1, n, k);
+    c.qy = load_var<T>(x, 2, n, k);
     c.z = x.zh[level_off(n) + k];
     return c;
 }
@@ -610,22 +660,7 @@ __device__ inline Cell<T> load_cell(const Fv1Ctx<T>& x, int n, uint32_t k)
 template <typename T>
 __device__ inline T load_h(const Fv1Ctx<T>& x, int n, uint32_t k)
 {
-    return n == x.L ? x.fin[0][k] : x.crs[0][level_off(n) + k];
-}
-
-// discharges and bed of the cell (n, k); h is already in c
-template <typename T>
-__device__ inline void load_rest(const Fv1Ctx<T>& x, int n, uint32_t k, Cell<T>& c)
-{
-    if (n == x.L) {
-        c.qx = x.fin[1][k];
-        c.qy = x.fin[2][k];
-    } else {
-        const uint64_t o = level_off(n) + k;
-        c.qx = x.crs[1][o];
-        c.qy = x.crs[2][o];
-    }
-    c.z = x.zh[level_off(n) + k];
+    return load_var<T>(x, 0, n, k);
 }
 
 // Same-level neighbour (Fig. 3) through the leaf-level map: the leaf that
@@ -824,13 +859,27 @@ __device__ inline void acc_flush(Acc& a, double (*red)[kPartial], double* rec)
     acc_reset(a);
 }
 
+// Finest cell k of the current set (the all-finest form of load_cell).
+template <typename T>
+__device__ inline Cell<T> load_fine(const Fv1Ctx<T>& x, uint32_t k)
+{
+    Cell<T> c;
+    c.h = ld_off(x.fin[0], k * (uint32_t)sizeof(T));
+    c.qx = ld_off(x.fin[1], k * (uint32_t)sizeof(T));
+    c.qy = ld_off(x.fin[2], k * (uint32_t)sizeof(T));
+    c.z = ld_off(x.zh, (uint32_t)((level_off(x.L) + k) * sizeof(double)));
+    return c;
+}
+
 // The full FV1 update of one leaf (the heavy kernel's path; waves whose
 // leaves are all dry take fv1_dry_write instead, which gives the same result).
-template <typename T>
+// FIN: the problem's leaves are all finest this step, so the leaf and its
+// neighbours are finest cells and no leaf-level byte is needed.
+template <typename T, bool FIN>
 __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
 {
     const int L = x.L;
-    const int m = level_of(idx);
+    const int m = FIN ? L : level_of(idx);
     const uint32_t c = idx - (uint32_t)level_off(m);
     const T g = (T)x.g;
     const T tol = (T)x.h_tol;
@@ -847,15 +896,15 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
     const uint32_t cE = inE ? morton_xp(c, xm, ym) : c;
     const uint32_t cS = inS ? morton_ym(c, xm, ym) : c;
     const uint32_t cN = inN ? morton_yp(c, xm, ym) : c;
-    const int lW = x.lmap[(uint64_t)cW << sh];
-    const int lE = x.lmap[(uint64_t)cE << sh];
-    const int lS = x.lmap[(uint64_t)cS << sh];
-    const int lN = x.lmap[(uint64_t)cN << sh];
-    const Cell<T> own = load_cell<T>(x, m, c);
-    const Cell<T> sW = load_cell<T>(x, m, cW);
-    const Cell<T> sE = load_cell<T>(x, m, cE);
-    const Cell<T> sS = load_cell<T>(x, m, cS);
-    const Cell<T> sN = load_cell<T>(x, m, cN);
+    const int lW = FIN ? L : x.lmap[(uint64_t)cW << sh];
+    const int lE = FIN ? L : x.lmap[(uint64_t)cE << sh];
+    const int lS = FIN ? L : x.lmap[(uint64_t)cS << sh];
+    const int lN = FIN ? L : x.lmap[(uint64_t)cN << sh];
+    const Cell<T> own = FIN ? load_fine<T>(x, c) : load_cell<T>(x, m, c);
+    const Cell<T> sW = FIN ? load_fine<T>(x, cW) : load_cell<T>(x, m, cW);
+    const Cell<T> sE = FIN ? load_fine<T>(x, cE) : load_cell<T>(x, m, cE);
+    const Cell<T> sS = FIN ? load_fine<T>(x, cS) : load_cell<T>(x, m, cS);
+    const Cell<T> sN = FIN ? load_fine<T>(x, cN) : load_cell<T>(x, m, cN);
     const Cell<T> w = inW ? neighbour_fix<T>(x, m, cW, lW, sW) : ghost_cell<T>(x, HW_W, own);
     const Cell<T> e = inE ? neighbour_fix<T>(x, m, cE, lE, sE) : ghost_cell<T>(x, HW_E, own);
     const Cell<T> so = inS ? neighbour_fix<T>(x, m, cS, lS, sS) : ghost_cell<T>(x, HW_S, own);
@@ -953,13 +1002,6 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
         acc.v[6] = 1.0;
 }
 
-// Pointer to the depth of the hierarchy cell (n, k): the finest set for
-// n = L, the coarse levels otherwise.
-template <typename T>
-__device__ inline gp<const T> h_ptr(const Fv1Ctx<T>& x, int n, uint32_t k)
-{
-    return n == x.L ? x.fin[0] + k : x.crs[0] + (level_off(n) + k);
-}
 
 // True when the west-edge inflow adds water to leaf (m, c) at time t.
 template <typename T>
@@ -1037,9 +1079,9 @@ __device__ inline void light_probe(const Fv1Ctx<T>& x, const uint32_t idx[kLeafB
         const int sh = 2 * (L - m);
 #pragma unroll
         for (int k = 0; k < 4; ++k) lv[u][k] = ld_off(x.lmap, nb[k] << sh);
-        hh[u][0] = *h_ptr<T>(x, m, c);
+        hh[u][0] = load_h<T>(x, m, c);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) hh[u][k + 1] = *h_ptr<T>(x, m, nb[k]);
+        for (int k = 0; k < 4; ++k) hh[u][k + 1] = load_h<T>(x, m, nb[k]);
         // c < 4^m <= 4^L, so c / 64 indexes the table even when unused
         b.e[u] = x.hist[uniform(c) >> 6];
     }
@@ -1057,7 +1099,7 @@ __device__ inline void light_probe(const Fv1Ctx<T>& x, const uint32_t idx[kLeafB
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (lv[u][k] < b.m[u])
-                    hh[u][k + 1] = *h_ptr<T>(x, lv[u][k], nb[k] >> (2 * (b.m[u] - lv[u][k])));
+                    hh[u][k + 1] = load_h<T>(x, lv[u][k], nb[k] >> (2 * (b.m[u] - lv[u][k])));
         }
     }
 #pragma unroll
@@ -1381,8 +1423,10 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
                 if ((k++ & (kBlock / kWave - 1)) != wid) continue;
                 const uint32_t w = (uint32_t)bit / kLeafBatch, u = (uint32_t)bit % kLeafBatch;
                 const uint32_t leaf = base + u * kBlock + w * kWave + (uint32_t)lane;
-                if (leaf < x.nl)
-                    fv1_leaf<T>(x, finest ? fin_off + leaf : x.leaves[leaf], acc);
+                if (leaf < x.nl) {
+                    if (finest) fv1_leaf<T, true>(x, fin_off + leaf, acc);
+                    else fv1_leaf<T, false>(x, x.leaves[leaf], acc);
+                }
             }
         }
     }
