@@ -149,7 +149,10 @@ typedef struct hw_scalars {
  *   zsig        static bed significance flags, (N-1)/3 bytes
  *   raw         significance of the current step before regularisation
  *   sig         significance after regularisation, (N-1)/3 bytes
- *   leaves      leaf list, capacity N uint32
+ *   leaves      leaf list, capacity N uint32; the time loop does not write
+ *               it in a step where every finest cell is a leaf (n_leaves =
+ *               N: the list is then the finest level in Morton order,
+ *               (N-1)/3 + m for m = 0..N-1)
  *   scal        one hw_scalars record
  *   work        scratch of hw_workspace_bytes() bytes, private to the
  *               library; between mra_traverse_leaves and fv1_step it carries

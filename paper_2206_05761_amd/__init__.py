@@ -227,7 +227,11 @@ class Buffers:
         return self.fine[cur]
 
     def leaf_list(self):
+        """The current leaf list.  When every finest cell is a leaf the time
+        loop does not write the list (it is the finest level in order)."""
         n = int(self.scalars()["n_leaves"])
+        if n == n_fine(self.problem.L):
+            return (np.arange(n, dtype=np.uint64) + n_coarse(self.problem.L)).astype(np.uint32)
         return self.leaves[:n].cpu().numpy().view(np.uint32)
 
 

@@ -202,7 +202,7 @@ Desc make_desc(const hw_problem* p, const hw_buffers* b, double* partials)
     for (int k = 0; k < 4; ++k) d.bc[k] = p->bc[k];
     d.group_level = group_level(p->L);
     d.write_skip = 1;
-    d.keep_parents = 1;   // the entry points store every level; plans do not
+    d.full_outputs = 1;   // the entry points write every output; plans do not
     d.eps = p->eps;
     d.g = p->g;
     d.cfl = p->cfl;
@@ -715,7 +715,7 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
             &problems[i], &buffers[i],
             pl->d_partials + 2 * (size_t)i * pl->fv1_grid * hw::kPartial));
         pl->host_desc.back().write_skip = pl->write_skip;
-        pl->host_desc.back().keep_parents = 0;
+        pl->host_desc.back().full_outputs = 0;
     }
     const bool single = n == 1;
     for (int k = 0; k < pl->passes; ++k)

@@ -41,7 +41,10 @@ struct Desc {
     double* partials;      // FV1 / ingest partial records, kPartial each
     uint32_t ntrav;        // traversal workgroups of this problem
     uint32_t nhist;        // entries of hist
-    int32_t keep_parents;  // store level L-1 of h, qx, qy when encoding
+    int32_t full_outputs;  // write every output (the entry points) or only
+                           // what the time loop reads (plans): coarse level
+                           // L-1, and the leaf list, leaf-level map and fill
+                           // table of a step whose leaves are all finest
     int32_t pad1;
 };
 

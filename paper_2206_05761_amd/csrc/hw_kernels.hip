@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     const double eps = d.eps;
     // Level L-1 of the flow variables is stored only when asked for (the
     // time loop reads it from the finest level instead, see parent_value).
-    const bool keep_parents = d.keep_parents != 0;
+    const bool keep_parents = d.full_outputs != 0;
 
     auto dst_of = [&](int v, int n) -> gp<T> { return dstb[v] + level_off(n); };
 
@@ -476,6 +476,9 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     const int s = scen_of(lc, blockIdx.x, lb);
     const Desc& d = lc.descs[s];
     if (d.scal->done) return;
+    // In the time loop a step whose leaves are all finest needs no list,
+    // map or fill table: the FV1 kernels take that case from n_leaves.
+    if (EMIT && !d.full_outputs && d.scal->n_leaves == (1ull << (2 * d.L))) return;
     const uint32_t ngroups = 1u << (2 * d.group_level);
     const uint32_t g = lb * kBlock + threadIdx.x;
     const bool active = g < ngroups;
@@ -1449,6 +1452,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(Launch lc)
     const Desc& d = lc.descs[s];
     const hw_scalars* sc = d.scal;
     if (sc->done) return;
+    if (sc->n_leaves == (1ull << (2 * d.L))) return;   // no coarser leaf at all
     const uint32_t g = lb * kBlock + threadIdx.x;
     if (g >= (1u << (2 * d.group_level))) return;
     const uint32_t src = glob(d.big_src)[g];
