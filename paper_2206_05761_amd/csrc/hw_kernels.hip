@@ -1088,6 +1088,7 @@ __device__ inline void light_probe(const Fv1Ctx<T>& x, const uint32_t idx[kLeafB
         // c < 4^m <= 4^L, so c / 64 indexes the table even when unused
         b.e[u] = x.hist[uniform(c) >> 6];
     }
+    __builtin_amdgcn_sched_barrier(0);
     bool coarser = false;
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -1142,11 +1143,17 @@ __device__ inline void light_probe_finest(const Fv1Ctx<T>& x, uint32_t base, Lig
         hh[u][4] = ld_off(x.fin[0], no * (uint32_t)sizeof(T));
         b.e[u] = x.hist[uniform(c) >> 6];
     }
+    // Keep every leaf's loads ahead of the first use (one round trip), and
+    // consume every loaded value on every path: a load still pending at the
+    // loop's back edge would make the next iteration wait for all memory
+    // operations, stores included.
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+        asm volatile("" ::"v"(b.e[u]));
         b.h[u] = hh[u][0];
-        b.dry[u] = hh[u][0] <= tol && hh[u][1] <= tol && hh[u][2] <= tol &&
-                   hh[u][3] <= tol && hh[u][4] <= tol && !inflow_on<T>(x, L, b.c[u]);
+        b.dry[u] = (hh[u][0] <= tol) & (hh[u][1] <= tol) & (hh[u][2] <= tol) &
+                   (hh[u][3] <= tol) & (hh[u][4] <= tol) & !inflow_on<T>(x, L, b.c[u]);
     }
 }
 
