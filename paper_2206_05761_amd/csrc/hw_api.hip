@@ -98,7 +98,7 @@ uint32_t encode_blocks(int L, int pass, int tl)
 }
 
 struct WorkLayout {
-    size_t desc, tcount, big_src, gcode, lmap, wet, hist, partials, total;
+    size_t desc, tcount, big_src, gcode, lmap, wet, hist, dryb, bpart, partials, total;
 };
 
 // Entries of the FV1 write history: one per 64-cell Morton block of the
@@ -123,6 +123,10 @@ WorkLayout work_layout(int L)
     o = align_up(o + 4 * ((size_t)hw_n_fine_(L) / (hw::kLeafBatch * hw::kBlock) + 1));
     w.hist = o;
     o = align_up(o + n_hist(L) * sizeof(uint64_t));
+    w.dryb = o;
+    o = align_up(o + n_hist(L));
+    w.bpart = o;
+    o = align_up(o + 2 * n_hist(L) * sizeof(double));
     w.partials = o;
     o = align_up(o + 2 * (size_t)hw::kMaxFv1Grid * hw::kPartial * sizeof(double));
     w.total = o;
@@ -235,6 +239,8 @@ Desc make_desc(const hw_problem* p, const hw_buffers* b, double* partials)
     d.gcode = reinterpret_cast<uint8_t*>(wk + w.gcode);
     d.wet = reinterpret_cast<uint8_t*>(wk + w.wet);
     d.hist = reinterpret_cast<uint64_t*>(wk + w.hist);
+    d.dryb = reinterpret_cast<uint8_t*>(wk + w.dryb);
+    d.bpart = reinterpret_cast<double*>(wk + w.bpart);
     d.nhist = (uint32_t)n_hist(p->L);
     d.partials = partials ? partials : reinterpret_cast<double*>(wk + w.partials);
     d.ntrav = n_trav(p->L);

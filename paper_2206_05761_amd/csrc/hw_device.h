@@ -38,6 +38,9 @@ struct Desc {
     uint8_t* gcode;        // per traversal group: walk summary (count pass)
     uint8_t* wet;          // FV1 wet table: 4 bytes per super-chunk
     uint64_t* hist;        // FV1 write history: one entry per 64 finest cells
+    uint8_t* dryb;         // per 64 finest cells: the dry case holds for all
+                           // of them (written by the first encoding pass)
+    double* bpart;         // per 64 finest cells: mass and max |h| (pairs)
     double* partials;      // FV1 / ingest partial records, kPartial each
     uint32_t ntrav;        // traversal workgroups of this problem
     uint32_t nhist;        // entries of hist

@@ -95,6 +95,30 @@ __device__ inline void load4(gp<const float> p, double o[4])
 // FLOW: h, qx, qy of the current step (flags OR-ed with the static bed
 // flags into raw); otherwise the bed (flags into zsig).
 
+// Inflow rate of the west-edge hydrograph at time t (the FV1 kernels'
+// inflow_rate, on a descriptor).
+__device__ inline double inflow_rate_d(const Desc& d, double t)
+{
+    if (!(d.q_peak > 0.0)) return 0.0;
+    if (t <= d.t_peak) return d.q_peak * t / d.t_peak;
+    if (t <= d.t_base) return d.q_peak * (d.t_base - t) / (d.t_base - d.t_peak);
+    return 0.0;
+}
+
+// Whether the inflow reaches the finest cell c at time t (inflow_on for a
+// finest leaf, on a descriptor).
+__device__ inline bool inflow_fine(const Desc& d, double t, uint32_t c)
+{
+    const uint32_t lvmask = 0xffffffffu >> (32 - 2 * d.L);
+    if ((c & 0x55555555u & lvmask) != 0 || !(d.q_peak > 0.0)) return false;
+    const double dym = ldexp(d.dy, 0);
+    const double y_lo = (double)compact1by1(c >> 1) * dym;
+    const double lo = y_lo > d.inlet_y0 ? y_lo : d.inlet_y0;
+    const double yhi = y_lo + dym;
+    const double hi = yhi < d.inlet_y1 ? yhi : d.inlet_y1;
+    return hi - lo > 0.0 && inflow_rate_d(d, t) != 0.0;
+}
+
 template <typename T, int NV, bool FLOW, bool DET, int CP>
 __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
                                                    int tl, double* details)
@@ -102,8 +126,15 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     uint32_t b;
     const int s = scen_of(lc, blockIdx.x, b);
     const Desc& d = lc.descs[s];
-    const hw_scalars* sc = d.scal;
-    if (FLOW && sc->done) return;
+    // every scalar this workgroup needs, requested together (one round trip)
+    const gp<const hw_scalars> sc = glob(static_cast<const hw_scalars*>(d.scal));
+    const uint32_t done = sc->done;
+    const int cur = uniform((int)sc->cur);
+    double smax_all[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) smax_all[v] = sc->smax[v];
+    const double t_now = sc->t;
+    if (FLOW && done) return;
     const int L = d.L;
     const int n_in = L - pass * tl;
     if (n_in <= 0) return;
@@ -113,7 +144,6 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     const int tid = threadIdx.x;
     const uint64_t ncoarse = level_off(L);
 
-    const int cur = uniform((int)sc->cur);
     gp<const T> src[NV];
     gp<T> dstb[NV];
     double smax[NV];
@@ -125,11 +155,11 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
                          : glob(reinterpret_cast<const T*>(d.coarse[v])) +
                                level_off(n_in);
             dstb[v] = glob(reinterpret_cast<T*>(d.coarse[v]));
-            smax[v] = sc->smax[v];
+            smax[v] = smax_all[v];
         } else {
             src[v] = glob(reinterpret_cast<const T*>(d.zhier)) + level_off(n_in);
             dstb[v] = glob(reinterpret_cast<T*>(d.zhier));
-            smax[v] = sc->smax[3];
+            smax[v] = smax_all[3];
         }
     }
     const gp<uint8_t> flags = glob(FLOW ? d.raw : d.zsig);
@@ -195,6 +225,67 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
         }
     }
 
+    // Block flags (first pass over the flow variables, L >= 5): for every
+    // 64-cell (8x8) Morton block of the tile, bit 0 = some depth above h_tol
+    // (or not a number), bit 1 = the inflow reaches one of its cells, bits
+    // 2..5 = some depth above h_tol in its west column, east column, south
+    // row, north row; and the block's mass and max |h|.  The FV1 step of a
+    // problem whose leaves are all finest treats a block as dry exactly when
+    // its bits 0 and 1 are clear and the edge of each neighbour block that
+    // touches it is dry (that is every cell's dry test), and takes its mass
+    // and max |h| from here instead of re-reading the depths.
+    const bool blocks = FLOW && pass == 0 && L >= 5;
+    const int cells = (CP == 1 || cp == 1) ? 4 : 16;    // finest cells per thread
+    const int tpb = 64 / cells;                         // threads per block
+    const T tolT = (T)d.h_tol;
+    auto block_test = [&](const double* hs) {
+        const uint64_t first = ((uint64_t)b << (2 * lv)) + (uint64_t)cells * tid;
+        const uint32_t blk = (uint32_t)(first >> 6);
+        const double tolD = (double)tolT;
+        const double area = d.dx * d.dy;
+        // this thread's square inside the block: side sq, corner (ti, tj)
+        const int sq = cells == 4 ? 2 : 4;
+        const uint32_t r = (uint32_t)(tid % tpb);
+        const int ti = (int)compact1by1(r) * sq, tj = (int)compact1by1(r >> 1) * sq;
+        bool wet = false, inflow = false, ww = false, we = false, ws = false, wn = false;
+        double m = 0.0, hm = 0.0;
+        for (int q = 0; q < cells; ++q) {
+            const bool w = !(hs[q] <= tolD);
+            const int ci = ti + (int)compact1by1((uint32_t)q);
+            const int cj = tj + (int)compact1by1((uint32_t)q >> 1);
+            wet = wet | w;
+            ww = ww | (w & (ci == 0));
+            we = we | (w & (ci == 7));
+            ws = ws | (w & (cj == 0));
+            wn = wn | (w & (cj == 7));
+            inflow = inflow | inflow_fine(d, t_now, (uint32_t)(first + q));
+            m += hs[q] * area;
+            const double a = fabs(hs[q]);
+            hm = a > hm ? a : hm;
+        }
+        // combine over the block's tpb consecutive lanes (aligned group)
+        const int lane = tid & (kWave - 1);
+        const uint64_t gmask = (tpb == 64 ? ~0ull : ((1ull << tpb) - 1ull)) << (lane & ~(tpb - 1));
+        const bool bw = (__ballot(wet) & gmask) != 0ull;
+        const bool bi = (__ballot(inflow) & gmask) != 0ull;
+        const bool bww = (__ballot(ww) & gmask) != 0ull;
+        const bool bwe = (__ballot(we) & gmask) != 0ull;
+        const bool bws = (__ballot(ws) & gmask) != 0ull;
+        const bool bwn = (__ballot(wn) & gmask) != 0ull;
+        for (int o = 1; o < tpb; o <<= 1) {
+            m += __shfl_xor(m, o);
+            const double y = __shfl_xor(hm, o);
+            hm = y > hm ? y : hm;
+        }
+        if ((lane & (tpb - 1)) == 0) {
+            glob(d.dryb)[blk] = (uint8_t)((bw ? 1 : 0) | (bi ? 2 : 0) | (bww ? 4 : 0) |
+                                          (bwe ? 8 : 0) | (bws ? 16 : 0) | (bwn ? 32 : 0));
+            gp<double> bp = glob(d.bpart) + 2ull * blk;
+            bp[0] = m;
+            bp[1] = hm;
+        }
+    };
+
     double p[NV];
     if ((uint32_t)tid < M) {
         const uint64_t tile_in = (uint64_t)b << (2 * lv);
@@ -209,6 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
 #pragma unroll
                     for (int q = 0; q < 4; ++q) ch[v][q] = (double)src[v][base + q];
             }
+            if (blocks) block_test(ch[0]);
             emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + tid, ch, p, zr[0]);
         } else {
             const uint64_t base = tile_in + 16ull * tid;
@@ -223,6 +315,14 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
                         for (int q = 0; q < 4; ++q)
                             ch[qq][v][q] = (double)src[v][base + 4 * qq + q];
                 }
+            if (blocks) {
+                double hs[16];
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) hs[4 * qq + q] = ch[qq][0][q];
+                block_test(hs);
+            }
             double mid[NV][4];
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) {
@@ -568,6 +668,8 @@ struct Fv1Ctx {
     gp<const uint8_t> lmap;
     gp<const uint32_t> leaves;
     gp<uint64_t> hist;     // write history (light kernel)
+    gp<const uint8_t> dryb;   // dry blocks and their mass / max |h|
+    gp<const double> bpart;
     uint64_t step;         // index of the step being taken
     int write_skip;        // stores of unchanged dry blocks may be skipped
     int L, Lg;
@@ -604,6 +706,8 @@ __device__ inline void make_ctx(Fv1Ctx<T>& x, const Desc& d)
     x.lmap = glob(static_cast<const uint8_t*>(d.lmap));
     x.leaves = glob(static_cast<const uint32_t*>(d.leaves));
     x.hist = glob(d.hist);
+    x.dryb = glob(static_cast<const uint8_t*>(d.dryb));
+    x.bpart = glob(static_cast<const double*>(d.bpart));
     x.step = sc->step;
     x.write_skip = d.write_skip;
     x.L = d.L;
@@ -1262,6 +1366,96 @@ __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre
     return f;
 }
 
+// The light kernel's pass over the 64-cell blocks of a problem whose
+// leaves are all finest (L >= 5): the first encoding pass has tested every
+// block (its own cells and the edge cells of its four neighbour blocks) and
+// summed its mass and max |h|, so one lane decides one block from a few
+// bytes, with every load in one round trip.  Lane t takes block t % 8 of
+// super-chunk sc0 + (t / 8) * stride (cnt super-chunks); a wet block sets
+// its bit in the super-chunk's wet word for the heavy kernel; a dry one adds
+// its mass and max |h| and, unless the write history allows skipping,
+// joins a list whose (h, 0, 0) stores all waves of the workgroup then share.
+template <typename T>
+__device__ inline void light_blocks(const Fv1Ctx<T>& x, gp<uint8_t> wetb, uint32_t sc0,
+                                    uint32_t stride, uint32_t cnt, Acc& acc,
+                                    uint32_t* slist, uint32_t& scount)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wid = tid / kWave;
+    const uint32_t j = (uint32_t)tid >> 3, bi = (uint32_t)tid & 7u;
+    const bool act = j < cnt;
+    const uint32_t sc = sc0 + (act ? j : 0u) * stride;
+    const uint32_t blk = 8u * sc + bi;
+    // block codes live on level L-3
+    const uint32_t bmask = 0xffffffffu >> (32 - 2 * (x.L - 3));
+    const uint32_t bxm = 0x55555555u & bmask, bym = 0xaaaaaaaau & bmask;
+    const bool hw = (blk & bxm) != 0, he = (blk & bxm) != bxm;
+    const bool hs = (blk & bym) != 0, hn = (blk & bym) != bym;
+    const uint32_t st = x.dryb[blk];
+    // the edge of each neighbour block that touches this one: the west
+    // neighbour's east column, and so on (the block's own byte, masked off,
+    // beyond the domain edge)
+    const uint32_t w = x.dryb[hw ? morton_xm(blk, bxm, bym) : blk];
+    const uint32_t e = x.dryb[he ? morton_xp(blk, bxm, bym) : blk];
+    const uint32_t so = x.dryb[hs ? morton_ym(blk, bxm, bym) : blk];
+    const uint32_t no = x.dryb[hn ? morton_yp(blk, bxm, bym) : blk];
+    const uint64_t eh = x.hist[blk];
+    const vd2 mh = *reinterpret_cast<gp<const vd2>>(x.bpart + 2ull * blk);
+    if (tid == 0) scount = 0u;
+    // bitwise, not short-circuit: a branch per neighbour would wait for each
+    // byte before loading the next
+    const uint32_t sn = (w & (hw ? 8u : 0u)) | (e & (he ? 4u : 0u)) |
+                        (so & (hs ? 32u : 0u)) | (no & (hn ? 16u : 0u));
+    const bool dry = x.rain_rate == 0.0 && (st & 3u) == 0u && sn == 0u;
+    bool skip = false;
+    if (act && x.write_skip) {
+        // the same record as for a wave's aligned block of 64 finest leaves
+        const bool valid = (eh >> 2) == x.step;
+        const uint64_t hb = ((valid ? (eh << 1) : 0ull) | (dry ? 1ull : 0ull)) & 3ull;
+        x.hist[blk] = ((x.step + 1) << 2) | hb;
+        skip = dry && valid && (eh & 3ull) == 3ull;
+    }
+    if (act && dry) {
+        acc.v[4] += mh.x;
+        acc_max(acc, 1, mh.y);
+    }
+    // wet word of the super-chunk: byte (block % 4), bit (block / 4)
+    uint32_t word = (act && !dry) ? 1u << (8u * (bi & 3u) + (bi >> 2)) : 0u;
+    word |= __shfl_xor(word, 1);
+    word |= __shfl_xor(word, 2);
+    word |= __shfl_xor(word, 4);
+    if (act && bi == 0u) *reinterpret_cast<gp<uint32_t>>(wetb + 4ull * sc) = word;
+    __syncthreads();   // scount cleared
+    const bool ns = act && dry && !skip;
+    const uint64_t m = __ballot(ns);
+    if (m) {
+        uint32_t at = 0u;
+        if (lane == 0) at = atomicAdd(&scount, (uint32_t)__popcll(m));
+        at = uniform(at);
+        if (ns) slist[at + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = blk;
+    }
+    __syncthreads();
+    const uint32_t nst = uniform(scount);
+    for (uint32_t k = (uint32_t)wid; k < nst; k += 2u * (kBlock / kWave)) {
+        const uint32_t k2 = k + kBlock / kWave;
+        const bool two = k2 < nst;
+        const uint32_t ca = 64u * uniform(slist[k]) + (uint32_t)lane;
+        const uint32_t cb = 64u * uniform(slist[two ? k2 : k]) + (uint32_t)lane;
+        const T ha = ld_off(x.fin[0], ca * (uint32_t)sizeof(T));
+        const T hb = ld_off(x.fin[0], cb * (uint32_t)sizeof(T));
+        x.fout[0][ca] = ha;
+        x.fout[1][ca] = T(0);
+        x.fout[2][ca] = T(0);
+        if (two) {
+            x.fout[0][cb] = hb;
+            x.fout[1][cb] = T(0);
+            x.fout[2][cb] = T(0);
+        }
+    }
+    __syncthreads();   // slist and scount are reused by the next pass
+}
+
 // FV1, light kernel: every leaf's dry probe; waves whose leaves are all
 // dry (no rain, no inflow on them) are finished here; the others are marked
 // in the wet table (one byte per super-chunk and wave, bit u for the wave's
@@ -1278,6 +1472,8 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
     const int wid = tid / kWave;
     for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
     __shared__ uint8_t mine[kMaxScen];
+    __shared__ uint32_t slist[kBlock];
+    __shared__ uint32_t scount;
     const int mode = FIN ? kFinestOnly : kMixedOnly;
     const Fv1Sched f = fv1_schedule(descs, n, cpre, mode, mine);
     // no problem of this kind this step: nothing to update and no records
@@ -1300,6 +1496,16 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
             wetb = glob(descs[s].wet);
             c0 = uniform(cpre[s]);
             c1 = uniform(cpre[s + 1]);
+        }
+        if (FIN && x.L >= 5) {
+            // up to 32 of this workgroup's super-chunks at once, all of the
+            // current problem
+            const uint32_t lim = f.c_end < c1 ? f.c_end : c1;
+            uint32_t cnt = (lim - ch + f.g8 - 1u) / f.g8;
+            cnt = cnt < 32u ? cnt : 32u;
+            light_blocks<T>(x, wetb, ch - c0, f.g8, cnt, acc, slist, scount);
+            ch += (cnt - 1u) * f.g8;
+            continue;
         }
         const uint32_t sc = ch - c0;
         const uint32_t base = sc * SC;
