@@ -38,17 +38,26 @@ def leaf_level_hist(buffers, L):
     return np.bincount(lvl, minlength=L + 1)
 
 
-def phase_bytes(L, w, hist):
+def phase_bytes(L, w, hist, dry=None):
     """Algorithmic HBM bytes of one step per phase (w = bytes per flow word).
 
     encode    read h, qx, qy on the finest level, write the coarse levels,
-              read the static bed flags, write the raw flags
+              read the static bed flags, write the raw flags; for L >= 5
+              also write one flag byte and a (mass, max |h|) pair per
+              64-cell block
     regularise read raw flags (one per cell, neighbours cached), write sig
     traverse  read sig along the walk (one pass over the coarse flags per
               kernel), write the leaf list and the fill table
-    fv1       per leaf: its index, own h, qx, qy and bed (FP64), and the
-              finest cells it writes (all descendants for leaves at or below
-              the traversal group level, one otherwise)
+    fv1       general step: per leaf its index, own h, qx, qy and bed (FP64),
+              and the finest cells it writes (all descendants for leaves at
+              or below the traversal group level, one otherwise).  A step
+              whose leaves are all finest, given dry = (stored, skipped) leaf
+              updates of the dry pass per step: the full update reads h, qx,
+              qy and z and writes h, qx, qy for the other leaves; a stored dry
+              leaf reads h and writes h, qx, qy; a skipped one moves nothing;
+              for L >= 5 every 64-cell block reads its flag byte, its history
+              word and its (mass, max |h|) pair and writes the history word
+              (neighbour flag bytes cached), and the wet table is written
     fill      the finest cells of coarser leaves
     """
     N = 4 ** L
@@ -65,11 +74,18 @@ def phase_bytes(L, w, hist):
             fv1_writes += cnt
             fill_writes += cnt * (4 ** (L - m) - 1)
     groups = 4 ** Lg
+    blocks = N // 64 if L >= 5 else 0
+    fv1 = nl * (4 + 3 * w + 8) + 3 * w * fv1_writes
+    if dry is not None and int(hist[L]) == N:
+        stored, skipped = dry
+        full = N - stored - skipped
+        fv1 = full * (3 * w + 8 + 3 * w) + stored * 4 * w + blocks * (1 + 8 + 16 + 8) \
+            + 4 * (N // 512)
     return {
-        "encode": 3 * w * N + 3 * w * Nc + 2 * Nc,
+        "encode": 3 * w * N + 3 * w * Nc + 2 * Nc + blocks * (1 + 16),
         "regularise": 2 * Nc,
         "traverse": 2 * Nc + 4 * nl + 4 * groups,
-        "fv1": nl * (4 + 3 * w + 8) + 3 * w * fv1_writes,
+        "fv1": int(fv1),
         "fill": 4 * groups + 3 * w * fill_writes,
         "finalize": 0,
         "n_leaves": nl,
@@ -108,6 +124,8 @@ def time_single(hw, w, precision, steps, warmup, prof_steps, tuning=None):
     s2 = sim.scalars()
     res = dict(sim=sim, plan=plan, ms=ms, wall=wall, steps=steps,
                leaf_updates=int(s1["leaf_updates"] - s0["leaf_updates"]),
+               dry=((s1["dry_stored"] - s0["dry_stored"]) / steps,
+                    (s1["dry_skipped"] - s0["dry_skipped"]) / steps),
                prof={k: v / prof_steps for k, v in prof.items()}, hist=hist,
                scalars=s2, tuning=best, tuning_table=table)
     return res
@@ -146,7 +164,7 @@ def load_traffic(phase, precision):
 
 
 def roofline(res, L, w, precision=None):
-    pb = phase_bytes(L, w, res["hist"])
+    pb = phase_bytes(L, w, res["hist"], res.get("dry"))
     prof = res["prof"]
     dom = max((k for k in prof), key=lambda k: prof[k])
     achieved = pb[dom] / (prof[dom] * 1e-3) / 1e9
@@ -165,6 +183,15 @@ def roofline(res, L, w, precision=None):
         "step_frac": round(total_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "phases": per_kernel,
     }
+
+
+def dry_split(res):
+    """Per-step leaf updates of the timed run: full update, and the dry pass
+    with stores written or skipped."""
+    stored, skipped = res["dry"]
+    per_step = res["leaf_updates"] / res["steps"]
+    return {"full": round(per_step - stored - skipped, 1), "dry_stored": round(stored, 1),
+            "dry_skipped": round(skipped, 1)}
 
 
 def fp32_error(hw, r64, r32):
@@ -311,6 +338,7 @@ def main():
                    "manning_n": w.params["manning_n"], "precision": "fp64"},
         "leaf_updates_per_s": r64["leaf_updates"] / (r64["ms"] * 1e-3),
         "n_leaves": int(r64["scalars"]["n_leaves"]),
+        "leaf_updates_per_step": dry_split(r64),
         "roofline": roofline(r64, L, 8, "fp64"),
         "tuning": r64["tuning"], "autotune_ms_per_step": r64["tuning_table"],
     }
@@ -323,6 +351,7 @@ def main():
             "value": round(args.steps / (rns["ms"] * 1e-3), 2), "unit": "timesteps/s",
             "ms_per_step": round(rns["ms"] / args.steps, 5),
             "fv1_ms": round(rns["prof"]["fv1"], 5),
+            "leaf_updates_per_step": dry_split(rns),
             "roofline": roofline(rns, L, 8),
             "note": "FP64, same workload and steps, fv1_write_skip=0",
         }
@@ -340,6 +369,7 @@ def main():
             "leaf_updates_per_s": rw["leaf_updates"] / (rw["ms"] * 1e-3),
             "n_leaves": int(rw["scalars"]["n_leaves"]),
             "wet_fraction": float((h_end > ww.params["h_tol"]).float().mean().item()),
+            "leaf_updates_per_step": dry_split(rw),
             "roofline": roofline(rw, L, 8),
             "tuning": rw["tuning"],
         }
@@ -353,6 +383,7 @@ def main():
             "value": round(args.steps / (r32["ms"] * 1e-3), 2), "unit": "timesteps/s",
             "ms_per_step": round(r32["ms"] / args.steps, 5),
             "leaf_updates_per_s": r32["leaf_updates"] / (r32["ms"] * 1e-3),
+            "leaf_updates_per_step": dry_split(r32),
             "roofline": roofline(r32, L, 4, "fp32_bulk"),
             "tuning": r32["tuning"],
             "error_vs_fp64": fp32_error(hw, r64, r32),

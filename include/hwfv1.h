@@ -129,6 +129,13 @@ typedef struct hw_scalars {
     uint64_t n_leaves;   /* leaves of the last traversal                   */
     uint64_t leaf_updates; /* sum of n_leaves over all steps               */
     uint64_t clips;      /* negative depths clipped to zero                */
+    uint64_t dry_stored; /* leaf updates done by the dry pass (a group of
+                            64 leaves, or a wave of them, all dry with dry
+                            neighbours: h kept, discharges zero), with
+                            their stores written                           */
+    uint64_t dry_skipped;/* the same with the stores skipped (the set being
+                            written already held the result); every other
+                            leaf update takes the full update              */
     uint32_t cur;        /* finest set (0 or 1) holding the current state  */
     uint32_t done;       /* 1 once t >= t_end                              */
     uint32_t nonfinite;  /* 1 if a non-finite value was produced           */
@@ -195,6 +202,8 @@ typedef struct hw_stats {
     uint64_t n_leaves;     /* leaves of the last step                      */
     uint64_t leaf_updates; /* leaf updates over the whole run              */
     uint64_t clips;
+    uint64_t dry_stored;   /* leaf updates of the dry pass, stores written */
+    uint64_t dry_skipped;  /* ... stores skipped (both over the whole run) */
     double wall_s;         /* host wall time of the call (s)               */
 } hw_stats;
 

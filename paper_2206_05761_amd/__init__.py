@@ -50,6 +50,7 @@ class HwScalars(C.Structure):
         ("maxspeed", C.c_double), ("acc", C.c_double * 6),
         ("step", C.c_uint64), ("n_leaves", C.c_uint64),
         ("leaf_updates", C.c_uint64), ("clips", C.c_uint64),
+        ("dry_stored", C.c_uint64), ("dry_skipped", C.c_uint64),
         ("cur", C.c_uint32), ("done", C.c_uint32), ("nonfinite", C.c_uint32),
         ("pad", C.c_uint32),
     ]
@@ -75,7 +76,8 @@ class HwStats(C.Structure):
         ("steps", C.c_int64), ("t", C.c_double), ("dt", C.c_double),
         ("mass0", C.c_double), ("mass", C.c_double),
         ("n_leaves", C.c_uint64), ("leaf_updates", C.c_uint64),
-        ("clips", C.c_uint64), ("wall_s", C.c_double),
+        ("clips", C.c_uint64), ("dry_stored", C.c_uint64),
+        ("dry_skipped", C.c_uint64), ("wall_s", C.c_double),
     ]
 
 

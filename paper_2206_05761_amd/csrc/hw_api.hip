@@ -449,6 +449,8 @@ int fill_stats(hw_plan* pl, const std::vector<uint64_t>& step0, hw_stats* stats,
             st.n_leaves = sc.n_leaves;
             st.leaf_updates = sc.leaf_updates;
             st.clips = sc.clips;
+            st.dry_stored = sc.dry_stored;
+            st.dry_skipped = sc.dry_skipped;
             st.wall_s = wall;
         }
         if (sc.nonfinite && rc == HW_OK)

@@ -11,7 +11,7 @@ namespace hw {
 constexpr int kBlock = 256;             // workgroup size of most kernels
 constexpr int kWave = 64;               // CDNA wavefront
 constexpr uint32_t kNone = 0xffffffffu; // "no coarse leaf" marker
-constexpr int kPartial = 8;             // doubles per FV1 partial record
+constexpr int kPartial = 10;            // doubles per FV1 partial record
 constexpr int kMaxScen = 64;            // problems per batch
 constexpr int kMaxFv1Grid = 8192;
 constexpr int kLeafBatch = 2;           // leaves per FV1 thread per iteration

@@ -915,7 +915,10 @@ struct Acc {
     double v[kPartial];
 };
 
-__device__ inline bool slot_is_sum(int q) { return q == 4 || q == 5; }
+// Record slots: 0 max wave speed, 1..3 max |h|, |qx|, |qy|, 4 mass, 5 clips,
+// 6 non-finite flag, 7 max |z| (ingest), 8 and 9 leaves finished by the dry
+// shortcut with their stores written or skipped.
+__device__ inline bool slot_is_sum(int q) { return q == 4 || q == 5 || q == 8 || q == 9; }
 
 __device__ inline void acc_reset(Acc& a)
 {
@@ -1277,6 +1280,8 @@ __device__ inline void fv1_dry_write(const Fv1Ctx<T>& x, int m, uint32_t c, T h,
     }
     acc_max(acc, 1, fabs((double)h));
     acc.v[4] += ((double)h * ldexp(x.dx, x.L - m)) * ldexp(x.dy, x.L - m);
+    acc.v[8] += store ? 1.0 : 0.0;
+    acc.v[9] += store ? 0.0 : 1.0;
 }
 
 // Write history of one wave's 64 leaves (wave-uniform).  When those leaves
@@ -1419,6 +1424,8 @@ __device__ inline void light_blocks(const Fv1Ctx<T>& x, gp<uint8_t> wetb, uint32
     if (act && dry) {
         acc.v[4] += mh.x;
         acc_max(acc, 1, mh.y);
+        acc.v[8] += skip ? 0.0 : 64.0;
+        acc.v[9] += skip ? 64.0 : 0.0;
     }
     // wet word of the super-chunk: byte (block % 4), bit (block / 4)
     uint32_t word = (act && !dry) ? 1u << (8u * (bi & 3u) + (bi >> 2)) : 0u;
@@ -1530,6 +1537,8 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
                     }
                     acc_max(acc, 1, fabs((double)b.h[u]));
                     acc.v[4] += (double)b.h[u] * area;
+                    acc.v[8] += skip ? 0.0 : 1.0;
+                    acc.v[9] += skip ? 1.0 : 0.0;
                 }
             }
         } else {
@@ -1752,6 +1761,8 @@ __global__ __launch_bounds__(kFinalBlock) void k_finalize(const Desc* descs,
         sc->step += 1;
         sc->leaf_updates += sc->n_leaves;
         sc->clips += (uint64_t)tot[5];
+        sc->dry_stored += (uint64_t)tot[8];
+        sc->dry_skipped += (uint64_t)tot[9];
         if (tot[6] > 0.0 || !isfinite(ms)) sc->nonfinite |= 1u;
         sc->cur ^= 1u;
         sc->done = (tn < d.t_end) ? 0u : 1u;
@@ -1848,6 +1859,8 @@ __global__ __launch_bounds__(kBlock) void k_ingest_final(const Desc* dd, int gri
         sc->n_leaves = 0;
         sc->leaf_updates = 0;
         sc->clips = 0;
+        sc->dry_stored = 0;
+        sc->dry_skipped = 0;
         sc->cur = 0;
         sc->done = (0.0 < d.t_end) ? 0u : 1u;
         sc->nonfinite = tot[6] > 0.0 ? 2u : 0u;

@@ -244,6 +244,36 @@ def dambreak_strip(L: int, h_left: float, h_right: float, x_dam: float,
                     meta=dict(h_left=h_left, h_right=h_right, x_dam=x_dam))
 
 
+def dry_patches(L: int, seed: int, n_rect: int = 4, n_single: int = 12,
+                inlet: bool = False, rain: float = 0.0) -> Workload:
+    """Mostly dry domain over a rough bed (uniform noise of 1 m on every
+    cell, so that every detail of z is significant and every leaf is
+    finest): a few wet rectangles and single wet cells of depth 0.3 m, and
+    cells whose depth equals h_tol (dry) or twice it (wet).  Drawn in that
+    order: bed, rectangle corners and sizes, single-cell positions, the
+    h_tol cells.  Optional west-edge inlet over the middle fifth and rain."""
+    rng = np.random.default_rng(seed)
+    n = 1 << L
+    tol = 1e-3
+    kw = dict(h_tol=tol, bc=("wall", "open", "wall", "open"), rain_rate=rain)
+    if inlet:
+        kw.update(inlet_y0=0.4, inlet_y1=0.6, q_peak=0.05, t_peak=1.0, t_base=2.0)
+    p = base_params(L, 1.0, 1e-3, **kw)
+    z = rng.uniform(0.0, 1.0, (n, n))
+    h = np.zeros((n, n))
+    for _ in range(n_rect):
+        j0, i0 = rng.integers(0, n, 2)
+        hj, hi = rng.integers(1, max(2, n // 8) + 1, 2)
+        h[j0:j0 + hj, i0:i0 + hi] = 0.3
+    jj, ii = rng.integers(0, n, (2, n_single))
+    h[jj, ii] = 0.3
+    jt, it = rng.integers(0, n, (2, n_single))
+    h[jt, it] = np.where(np.arange(n_single) % 2 == 0, tol, 2 * tol)
+    zero = np.zeros_like(h)
+    return Workload(f"dry_patches_l{L}", p, h, zero, zero.copy(), z,
+                    n_steps=10, meta=dict(seed=seed))
+
+
 BY_NAME = {
     "dambreak_bumps_l6": dambreak_bumps_l6,
     "circular_dambreak_l10": circular_dambreak_l10,
