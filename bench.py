@@ -41,10 +41,11 @@ def leaf_level_hist(buffers, L):
 def phase_bytes(L, w, hist, dry=None):
     """Algorithmic HBM bytes of one step per phase (w = bytes per flow word).
 
-    encode    read h, qx, qy on the finest level, write the coarse levels,
-              read the static bed flags, write the raw flags; for L >= 5
-              also write one flag byte and a (mass, max |h|) pair per
-              64-cell block
+    encode    read h, qx, qy on the finest level, write the coarse levels
+              0..L-2 (the time loop does not store level L-1: its values are
+              recomputed from the finest level where needed), read the
+              static bed flags, write the raw flags; for L >= 5 also write
+              one flag byte and a (mass, max |h|) pair per 64-cell block
     regularise read raw flags (one per cell, neighbours cached), write sig
     traverse  read sig along the walk (one pass over the coarse flags per
               kernel), write the leaf list and the fill table
@@ -82,7 +83,7 @@ def phase_bytes(L, w, hist, dry=None):
         fv1 = full * (3 * w + 8 + 3 * w) + stored * 4 * w + blocks * (1 + 8 + 16 + 8) \
             + 4 * (N // 512)
     return {
-        "encode": 3 * w * N + 3 * w * Nc + 2 * Nc + blocks * (1 + 16),
+        "encode": 3 * w * N + 3 * w * (Nc - 4 ** (L - 1)) + 2 * Nc + blocks * (1 + 16),
         "regularise": 2 * Nc,
         "traverse": 2 * Nc + 4 * nl + 4 * groups,
         "fv1": int(fv1),

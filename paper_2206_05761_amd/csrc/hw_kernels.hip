@@ -89,8 +89,9 @@ __device__ inline void load4(gp<const float> p, double o[4])
 // A pass covers `tl` levels: the workgroup owns a tile of 4^lv cells of the
 // input level n_in (lv = min(tl, n_in)) and produces levels n_in-1 .. n_in-lv.
 // Each thread first reduces 4^cp consecutive input cells in registers (cp = 1
-// or 2 levels), the remaining levels go through LDS.  Pass 0 reads the
-// finest level; pass k reads the coarse level written by pass k-1.
+// or 2 levels); their values meet in LDS once, and the first wave produces
+// the remaining levels (lane shuffles, no further barrier).  Pass 0 reads
+// the finest level; pass k reads the coarse level written by pass k-1.
 //
 // FLOW: h, qx, qy of the current step (flags OR-ed with the static bed
 // flags into raw); otherwise the bed (flags into zsig).
@@ -105,18 +106,19 @@ __device__ inline double inflow_rate_d(const Desc& d, double t)
     return 0.0;
 }
 
-// Whether the inflow reaches the finest cell c at time t (inflow_on for a
-// finest leaf, on a descriptor).
-__device__ inline bool inflow_fine(const Desc& d, double t, uint32_t c)
+// Whether the inflow reaches the finest cell c (inflow_on for a finest
+// leaf), given whether it flows at all now and the inlet (y0, y1) and cell
+// height dy.
+__device__ inline bool inflow_fine(bool flowing, double y0, double y1, double dy, int L,
+                                   uint32_t c)
 {
-    const uint32_t lvmask = 0xffffffffu >> (32 - 2 * d.L);
-    if ((c & 0x55555555u & lvmask) != 0 || !(d.q_peak > 0.0)) return false;
-    const double dym = ldexp(d.dy, 0);
-    const double y_lo = (double)compact1by1(c >> 1) * dym;
-    const double lo = y_lo > d.inlet_y0 ? y_lo : d.inlet_y0;
-    const double yhi = y_lo + dym;
-    const double hi = yhi < d.inlet_y1 ? yhi : d.inlet_y1;
-    return hi - lo > 0.0 && inflow_rate_d(d, t) != 0.0;
+    const uint32_t lvmask = 0xffffffffu >> (32 - 2 * L);
+    if (!flowing || (c & 0x55555555u & lvmask) != 0) return false;
+    const double y_lo = (double)compact1by1(c >> 1) * dy;
+    const double lo = y_lo > y0 ? y_lo : y0;
+    const double yhi = y_lo + dy;
+    const double hi = yhi < y1 ? yhi : y1;
+    return hi - lo > 0.0;
 }
 
 template <typename T, int NV, bool FLOW, bool DET, int CP>
@@ -238,11 +240,16 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     const int cells = (CP == 1 || cp == 1) ? 4 : 16;    // finest cells per thread
     const int tpb = 64 / cells;                         // threads per block
     const T tolT = (T)d.h_tol;
+    // everything the block test reads from the descriptor, read once
+    const double area = d.dx * d.dy, cell_dy = d.dy;
+    const double in_y0 = d.inlet_y0, in_y1 = d.inlet_y1;
+    const bool flowing = blocks && d.q_peak > 0.0 && inflow_rate_d(d, t_now) != 0.0;
+    const gp<uint8_t> dryb = glob(d.dryb);
+    const gp<double> bpart = glob(d.bpart);
     auto block_test = [&](const double* hs) {
         const uint64_t first = ((uint64_t)b << (2 * lv)) + (uint64_t)cells * tid;
         const uint32_t blk = (uint32_t)(first >> 6);
         const double tolD = (double)tolT;
-        const double area = d.dx * d.dy;
         // this thread's square inside the block: side sq, corner (ti, tj)
         const int sq = cells == 4 ? 2 : 4;
         const uint32_t r = (uint32_t)(tid % tpb);
@@ -258,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
             we = we | (w & (ci == 7));
             ws = ws | (w & (cj == 0));
             wn = wn | (w & (cj == 7));
-            inflow = inflow | inflow_fine(d, t_now, (uint32_t)(first + q));
+            inflow = inflow | inflow_fine(flowing, in_y0, in_y1, cell_dy, L, (uint32_t)(first + q));
             m += hs[q] * area;
             const double a = fabs(hs[q]);
             hm = a > hm ? a : hm;
@@ -278,9 +285,9 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
             hm = y > hm ? y : hm;
         }
         if ((lane & (tpb - 1)) == 0) {
-            glob(d.dryb)[blk] = (uint8_t)((bw ? 1 : 0) | (bi ? 2 : 0) | (bww ? 4 : 0) |
+            dryb[blk] = (uint8_t)((bw ? 1 : 0) | (bi ? 2 : 0) | (bww ? 4 : 0) |
                                           (bwe ? 8 : 0) | (bws ? 16 : 0) | (bwn ? 32 : 0));
-            gp<double> bp = glob(d.bpart) + 2ull * blk;
+            gp<double> bp = bpart + 2ull * blk;
             bp[0] = m;
             bp[1] = hm;
         }
@@ -336,32 +343,31 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
         }
     }
 
-    // Remaining levels of the tile through LDS.
-    __shared__ double lds[2][NV][kBlock];
+    // Remaining levels of the tile: every thread's value goes to LDS once,
+    // then the first wave alone carries on (the other waves are done): lane
+    // j takes the children of cell j of the next level from LDS, and each
+    // further level gathers its four children from lanes 4j..4j+3.
+    __shared__ double lds[NV][kBlock];
     if ((uint32_t)tid < M) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) lds[0][v][tid] = p[v];
+        for (int v = 0; v < NV; ++v) lds[v][tid] = p[v];
     }
     __syncthreads();
-    int pp = 0;
+    if (tid >= kWave) return;
     uint32_t cnt = M;
 #pragma unroll
     for (int i = 0; i < kTail; ++i) {
         const int n = n_mid - 1 - i;
         if (n < n_lo) break;
         cnt >>= 2;
-        if ((uint32_t)tid < cnt) {
-            double ch[NV][4];
+        double ch[NV][4];
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                for (int q = 0; q < 4; ++q) ch[v][q] = lds[pp][v][4 * tid + q];
-            double o[NV];
-            emit(n, (uint64_t)b * cnt + tid, ch, o, zt[i]);
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) lds[pp ^ 1][v][tid] = o[v];
-        }
-        __syncthreads();
-        pp ^= 1;
+            for (int q = 0; q < 4; ++q)
+                ch[v][q] = i == 0 ? lds[v][(4 * tid + q) & (kBlock - 1)]
+                                  : __shfl(p[v], (4 * tid + q) & (kWave - 1));
+        if ((uint32_t)tid < cnt) emit(n, (uint64_t)b * cnt + tid, ch, p, zt[i]);
     }
 }
 
