@@ -1341,17 +1341,10 @@ __device__ inline bool all_finest(const Desc& d, uint64_t n_leaves)
     return n_leaves == (1ull << (2 * d.L));
 }
 
-// Problems taken by a kernel: every problem (kAllProblems), only those whose
-// leaves are all finest (kFinestOnly), or only the others (kMixedOnly).
-enum { kAllProblems = 0, kFinestOnly = 1, kMixedOnly = 2 };
-
-__device__ inline bool takes(int mode, const Desc& d, uint64_t nl)
-{
-    return mode == kAllProblems || (mode == kFinestOnly) == all_finest(d, nl);
-}
-
+// Chunk prefix over the problems that are stepping; optionally, per
+// problem, whether it steps (mine) and whether its leaves are all finest.
 __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre,
-                                        int mode = kAllProblems, uint8_t* mine = nullptr)
+                                        uint8_t* mine = nullptr, uint8_t* finest = nullptr)
 {
     constexpr uint32_t SC = kLeafBatch * kBlock;
     if (threadIdx.x == 0) {
@@ -1360,8 +1353,9 @@ __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre
             cpre[s] = a;
             const hw_scalars* sc = descs[s].scal;
             const uint64_t nl = sc->n_leaves;
-            const bool m = !sc->done && takes(mode, descs[s], nl);
+            const bool m = !sc->done;
             if (mine) mine[s] = m ? 1 : 0;
+            if (finest) finest[s] = all_finest(descs[s], nl) ? 1 : 0;
             a += m ? ((uint32_t)nl + SC - 1) / SC : 0u;
         }
         cpre[n] = a;
@@ -1472,8 +1466,11 @@ __device__ inline void light_blocks(const Fv1Ctx<T>& x, gp<uint8_t> wetb, uint32
 // FV1, light kernel: every leaf's dry probe; waves whose leaves are all
 // dry (no rain, no inflow on them) are finished here; the others are marked
 // in the wet table (one byte per super-chunk and wave, bit u for the wave's
-// u-th sub-chunk) for the heavy kernel.  Records go to slots [0, gridDim.x).
-template <typename T, bool FIN>
+// u-th sub-chunk) for the heavy kernel.  A problem whose leaves are all
+// finest this step takes the dry pass over 64-cell blocks (L >= 5) or the
+// finest-leaf probe; the others the general probe (leaf list, leaf-level
+// map, coarser neighbours).  Records go to slots [0, gridDim.x).
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ descs, int n)
 {
     constexpr int U = kLeafBatch;
@@ -1485,12 +1482,12 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
     const int wid = tid / kWave;
     for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
     __shared__ uint8_t mine[kMaxScen];
+    __shared__ uint8_t finest[kMaxScen];
     __shared__ uint32_t slist[kBlock];
     __shared__ uint32_t scount;
-    const int mode = FIN ? kFinestOnly : kMixedOnly;
-    const Fv1Sched f = fv1_schedule(descs, n, cpre, mode, mine);
-    // no problem of this kind this step: nothing to update and no records
-    // to write (finalize reads records of problems that are stepping only)
+    const Fv1Sched f = fv1_schedule(descs, n, cpre, mine, finest);
+    // no problem is stepping: nothing to update and no records to write
+    // (finalize reads records of problems that are stepping only)
     if (uniform(cpre[n]) == 0u) return;
     Acc acc;
     acc_reset(acc);
@@ -1498,6 +1495,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
     Fv1Ctx<T> x;
     uint32_t c0 = 0, c1 = 0;
     gp<uint8_t> wetb = gp<uint8_t>(nullptr);
+    bool fin = false;
     for (uint32_t ch = f.c_begin; ch < f.c_end; ch += f.g8) {
         if (cs < 0 || ch >= c1) {
             int s = cs < 0 ? 0 : cs;
@@ -1509,8 +1507,9 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
             wetb = glob(descs[s].wet);
             c0 = uniform(cpre[s]);
             c1 = uniform(cpre[s + 1]);
+            fin = uniform((int)finest[s]) != 0;
         }
-        if (FIN && x.L >= 5) {
+        if (fin && x.L >= 5) {
             // up to 32 of this workgroup's super-chunks at once, all of the
             // current problem
             const uint32_t lim = f.c_end < c1 ? f.c_end : c1;
@@ -1524,7 +1523,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
         const uint32_t base = sc * SC;
         LightBatch<T> b;
         uint32_t bits = 0;
-        if (FIN) {
+        if (fin) {
             light_probe_finest<T>(x, base, b);
             // every full wave is one aligned 64-cell block of finest leaves
             const double area = x.dx * x.dy;
@@ -1564,8 +1563,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
     }
     if (cs >= 0) acc_flush(acc, red, rec[cs]);
     __syncthreads();
-    // records only for the problems this kernel takes (the other light
-    // kernel writes the same slots for the rest)
+    // records of the problems that are stepping
     for (int q = tid; q < n * kPartial; q += kBlock) {
         const int s = q / kPartial;
         if (mine[s])
@@ -1990,12 +1988,10 @@ hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
     (void)waves;
     const uint32_t gh = heavy_grid(grid);
     if (prec == HW_FP64) {
-        hipLaunchKernelGGL((k_fv1_light<double, true>), dim3(grid), dim3(kBlock), 0, s, descs, n);
-        hipLaunchKernelGGL((k_fv1_light<double, false>), dim3(grid), dim3(kBlock), 0, s, descs, n);
+        hipLaunchKernelGGL(k_fv1_light<double>, dim3(grid), dim3(kBlock), 0, s, descs, n);
         hipLaunchKernelGGL(k_fv1_heavy<double>, dim3(gh), dim3(kBlock), 0, s, descs, n, grid);
     } else {
-        hipLaunchKernelGGL((k_fv1_light<float, true>), dim3(grid), dim3(kBlock), 0, s, descs, n);
-        hipLaunchKernelGGL((k_fv1_light<float, false>), dim3(grid), dim3(kBlock), 0, s, descs, n);
+        hipLaunchKernelGGL(k_fv1_light<float>, dim3(grid), dim3(kBlock), 0, s, descs, n);
         hipLaunchKernelGGL(k_fv1_heavy<float>, dim3(gh), dim3(kBlock), 0, s, descs, n, grid);
     }
     return hipGetLastError();
