@@ -38,7 +38,7 @@ def leaf_level_hist(buffers, L):
     return np.bincount(lvl, minlength=L + 1)
 
 
-def phase_bytes(L, w, hist, dry=None):
+def phase_bytes(L, w, hist, dry=None, uniform=False):
     """Algorithmic HBM bytes of one step per phase (w = bytes per flow word).
 
     encode    read h, qx, qy on the finest level, write the coarse levels
@@ -60,6 +60,11 @@ def phase_bytes(L, w, hist, dry=None):
               word and its (mass, max |h|) pair and writes the history word
               (neighbour flag bytes cached), and the wet table is written
     fill      the finest cells of coarser leaves
+
+    uniform FV1 plan (FV1 and finalize only): every finest cell reads its
+    depth (neighbours cached); the full update reads h, qx, qy and z and
+    writes h, qx, qy; a stored dry cell writes h, qx, qy; each 64-cell block
+    reads and writes its history word; the wet table is written
     """
     N = 4 ** L
     Nc = (N - 1) // 3
@@ -76,6 +81,13 @@ def phase_bytes(L, w, hist, dry=None):
             fill_writes += cnt * (4 ** (L - m) - 1)
     groups = 4 ** Lg
     blocks = N // 64 if L >= 5 else 0
+    if uniform:
+        stored, skipped = dry
+        full = N - stored - skipped
+        fv1 = full * (3 * w + 8 + 3 * w) + stored * 4 * w + skipped * w \
+            + (N // 64) * 16 + 4 * (N // 512)
+        return {"encode": 0, "regularise": 0, "traverse": 0, "fv1": int(fv1), "fill": 0,
+                "finalize": 0, "n_leaves": N}
     fv1 = nl * (4 + 3 * w + 8) + 3 * w * fv1_writes
     if dry is not None and int(hist[L]) == N:
         stored, skipped = dry
@@ -93,7 +105,7 @@ def phase_bytes(L, w, hist, dry=None):
     }
 
 
-def time_single(hw, w, precision, steps, warmup, prof_steps, tuning=None):
+def time_single(hw, w, precision, steps, warmup, prof_steps, tuning=None, uniform=False):
     import torch
     from paper_2206_05761_amd.autotune import autotune
     log(f"[bench] {w.name} {precision}: ingest")
@@ -104,7 +116,7 @@ def time_single(hw, w, precision, steps, warmup, prof_steps, tuning=None):
     else:
         best, table = dict(tuning), None
         log(f"[bench] {precision}: fixed tuning {best}")
-    plan = hw.Plan([sim.problem], [sim.buffers], tuning=best)
+    plan = hw.Plan([sim.problem], [sim.buffers], tuning=best, uniform=uniform)
     hw.hwfv1_run(sim.problem, sim.buffers, warmup, plan=plan, stats=True)
     s0 = sim.scalars()
     torch.cuda.synchronize()
@@ -128,7 +140,7 @@ def time_single(hw, w, precision, steps, warmup, prof_steps, tuning=None):
                dry=((s1["dry_stored"] - s0["dry_stored"]) / steps,
                     (s1["dry_skipped"] - s0["dry_skipped"]) / steps),
                prof={k: v / prof_steps for k, v in prof.items()}, hist=hist,
-               scalars=s2, tuning=best, tuning_table=table)
+               scalars=s2, tuning=best, tuning_table=table, uniform=uniform)
     return res
 
 
@@ -165,8 +177,8 @@ def load_traffic(phase, precision):
 
 
 def roofline(res, L, w, precision=None):
-    pb = phase_bytes(L, w, res["hist"], res.get("dry"))
-    prof = res["prof"]
+    pb = phase_bytes(L, w, res["hist"], res.get("dry"), res.get("uniform", False))
+    prof = {k: v for k, v in res["prof"].items() if v > 0}
     dom = max((k for k in prof), key=lambda k: prof[k])
     achieved = pb[dom] / (prof[dom] * 1e-3) / 1e9
     step_ms = sum(prof.values())
@@ -260,6 +272,55 @@ def bench_batch(hw, steps, warmup, n_members):
     return out
 
 
+def run_to_end_ms(hw, w, uniform):
+    """Milliseconds (HIP events) of a FP64 run from the workload's initial
+    state to its t_end, on a plan that has already been captured: a first
+    run counts the steps, the state is ingested again and exactly that many
+    steps are timed."""
+    import numpy as np
+    import torch
+    sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision="fp64")
+    plan = hw.Plan([sim.problem], [sim.buffers], uniform=uniform)
+    st = hw.hwfv1_run(sim.problem, sim.buffers, 10 ** 7, plan=plan, stats=True)
+    n = st["steps"]
+    leaves = st["leaf_updates"] / max(n, 1)
+    dev = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1), device="cuda")
+           for a in (w.h, w.qx, w.qy, w.z)]
+    hw.hw_ingest(sim.problem, sim.buffers, *dev)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hw.hwfv1_run(sim.problem, sim.buffers, n, plan=plan, stats=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    t = sim.scalars()["t"]
+    plan.close()
+    sim.close()
+    return ms, n, leaves, t
+
+
+def bench_speedup(hw, levels=(8, 9, 10, 11, 12), epss=(1e-4, 1e-3, 1e-2)):
+    """Speed-up of HWFV1 over uniform FV1 to reach t = 3.5 s in the circular
+    dam break (the paper's Fig. 12 configurations, and L = 12)."""
+    import workloads as W
+    rows = []
+    for L in levels:
+        um, un, _, _ = run_to_end_ms(hw, W.circular_dambreak_flat(L), True)
+        for eps in epss:
+            ms, n, leaves, t = run_to_end_ms(hw, W.circular_dambreak_flat(L, eps), False)
+            rows.append({"L": L, "eps": eps, "steps": n, "hwfv1_ms": round(ms, 3),
+                         "uniform_fv1_ms": round(um, 3), "speedup": round(um / ms, 3),
+                         "mean_leaf_fraction": round(leaves / 4 ** L, 4)})
+            log(f"[bench] speed-up L={L} eps={eps}: {n} steps, HWFV1 {ms:.1f} ms, "
+                f"uniform {um:.1f} ms ({un} steps), x{um / ms:.2f}, "
+                f"leaves {leaves / 4 ** L:.3f}")
+    return {"workload": "circular_dambreak_flat (closed 40 m square, flat, frictionless, "
+                        "2.5 m / 0.5 m, dam radius 2.5 m off-centre by (1.3, 0.7) m, to t = 3.5 s)",
+            "precision": "fp64", "unit": "ms to t_end (HIP events)", "rows": rows}
+
+
 def cpu_baseline(w, n_steps):
     import oracle as O
     log(f"[bench] cpu oracle: {n_steps} steps of {w.name}")
@@ -286,6 +347,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-speedup", action="store_true",
+                    help="skip the uniform-FV1 comparisons")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the no-write-skip and fully wet FP64 runs")
     ap.add_argument("--tuning", default=None, metavar="CPT,GRID",
@@ -377,6 +440,24 @@ def main():
         rw["plan"].close()
         rw["sim"].close()
         del rw, h_end
+    if not args.no_speedup:
+        # The same workload and steps on the uniform FV1 plan (every finest
+        # cell updated, no multiresolution phases).
+        ru = time_single(hw, w, "fp64", args.steps, args.warmup, args.prof_steps,
+                         r64["tuning"], uniform=True)
+        uv = args.steps / (ru["ms"] * 1e-3)
+        line["uniform_fv1"] = {
+            "workload": w.name, "value": round(uv, 2), "unit": "timesteps/s",
+            "ms_per_step": round(ru["ms"] / args.steps, 5),
+            "hwfv1_over_uniform": round(value / uv, 3),
+            "leaf_updates_per_step": dry_split(ru),
+            "roofline": roofline(ru, L, 8),
+            "note": "FP64 uniform FV1 plan, same workload, steps and FV1 launch shape",
+        }
+        ru["plan"].close()
+        ru["sim"].close()
+        del ru
+        line["speedup_series"] = bench_speedup(hw)
     if not args.no_fp32:
         r32 = time_single(hw, w, "fp32_bulk", args.steps, args.warmup, args.prof_steps,
                           tuning)

@@ -310,6 +310,21 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
 int hw_plan_destroy(hw_plan* plan);
 
 /*
+ * Uniform FV1 plan: the comparison the paper measures its speed-ups against
+ * (FV1 on the finest uniform grid, Sections 1 and 3).  Every step updates
+ * every finest cell with its four face neighbours (the FV1 step above with
+ * all 4^L finest cells as leaves) and then finalises t, dt, s_max and mass;
+ * no encoding, flagging or traversal runs, and eps is ignored.  The result
+ * equals HWFV1 with eps = 0.  Arguments, ownership and errors as for
+ * hw_plan_create; run it with hwfv1_run (one problem) or hwfv1_run_batch.
+ * The coarse levels, flags and leaf list are not written; hw_scalars.n_leaves
+ * reads 4^L after the first step.
+ */
+int hw_plan_create_uniform(hw_plan** out, const hw_problem* problems,
+                           const hw_buffers* buffers, int32_t n,
+                           const hw_tuning* tuning);
+
+/*
  * Batched ensemble: advance the plan's n independent problems (each with
  * its own L, eps, physics, t and dt) by max_steps lockstep steps, one launch
  * per phase covering all problems, captured as one graph per step.  stats

@@ -112,6 +112,8 @@ def lib():
                                 P(HwStats), vp]
         L.hw_plan_create.argtypes = [P(vp), P(HwProblem), P(HwBuffers),
                                      C.c_int32, P(HwTuning)]
+        L.hw_plan_create_uniform.argtypes = [P(vp), P(HwProblem), P(HwBuffers),
+                                             C.c_int32, P(HwTuning)]
         L.hw_plan_destroy.argtypes = [vp]
         L.hwfv1_run_batch.argtypes = [vp, C.c_int64, P(HwStats), vp]
         L.hw_export.argtypes = [P(HwProblem), P(HwBuffers), vp, vp, vp, vp]
@@ -303,9 +305,10 @@ def hwfv1_run(problem, buffers, max_steps, plan=None, stats=True, stream=None):
 
 class Plan:
     """Descriptors, launch shapes and the captured step graph of 1..64
-    problems."""
+    problems.  uniform=True makes a uniform FV1 plan (every finest cell
+    updated each step, no multiresolution phases)."""
 
-    def __init__(self, problems, buffers, tuning=None):
+    def __init__(self, problems, buffers, tuning=None, uniform=False):
         n = len(problems)
         self._probs = (HwProblem * n)(*problems)
         self._bufs = (HwBuffers * n)(*[b.c for b in buffers])
@@ -318,9 +321,11 @@ class Plan:
                           int(tuning.get("fv1_grid", 0)),
                           int(tuning.get("fv1_write_skip", 1)))
         h = C.c_void_p()
-        _check(lib().hw_plan_create(C.byref(h), self._probs, self._bufs, n,
-                                    C.byref(tu) if tu is not None else None))
+        create = lib().hw_plan_create_uniform if uniform else lib().hw_plan_create
+        _check(create(C.byref(h), self._probs, self._bufs, n,
+                      C.byref(tu) if tu is not None else None))
         self.handle = h
+        self.uniform = bool(uniform)
 
     def close(self):
         if self.handle:

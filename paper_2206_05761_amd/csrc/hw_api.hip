@@ -296,6 +296,7 @@ struct hw_plan {
     int tl = 5, cp = 1;
     uint32_t fv1_grid = 8;
     int write_skip = 1;
+    bool uniform = false;                     // uniform FV1 plan (FV1 and finalize only)
     std::vector<hw_problem> problems;
     std::vector<hw_buffers> buffers;
     std::vector<Desc> host_desc;
@@ -324,6 +325,9 @@ hipError_t enqueue_phase(hw_plan* pl, int phase, hipStream_t s)
 {
     hipError_t e = hipSuccess;
     const int n = pl->n;
+    // a uniform FV1 plan updates every finest cell: no encoding, flags,
+    // traversal or copy-down
+    if (pl->uniform && phase != HW_PH_FV1 && phase != HW_PH_FINALIZE) return e;
     switch (phase) {
     case HW_PH_ENCODE:
         for (int k = 0; k < pl->passes && e == hipSuccess; ++k) {
@@ -599,8 +603,10 @@ int hw_export(const hw_problem* p, const hw_buffers* b, double* h, double* qx,
     return ok();
 }
 
-int hw_plan_create(hw_plan** out, const hw_problem* problems,
-                   const hw_buffers* buffers, int32_t n, const hw_tuning* tuning)
+// Plan of n problems; uniform: every step is the FV1 update of every finest
+// cell (no encoding, flags or traversal).
+static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffers* buffers,
+                       int32_t n, const hw_tuning* tuning, bool uniform)
 {
     if (!out) return fail(HW_EINVAL, "plan output pointer is NULL");
     *out = nullptr;
@@ -620,6 +626,7 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
     hw_plan* pl = new (std::nothrow) hw_plan;
     if (!pl) return fail(HW_EINVAL, "out of host memory");
     pl->n = n;
+    pl->uniform = uniform;
     pl->precision = problems[0].precision;
     pl->problems.assign(problems, problems + n);
     pl->buffers.assign(buffers, buffers + n);
@@ -724,6 +731,7 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
             pl->d_partials + 2 * (size_t)i * pl->fv1_grid * hw::kPartial));
         pl->host_desc.back().write_skip = pl->write_skip;
         pl->host_desc.back().full_outputs = 0;
+        pl->host_desc.back().uniform = uniform ? 1 : 0;
     }
     const bool single = n == 1;
     for (int k = 0; k < pl->passes; ++k)
@@ -740,6 +748,18 @@ int hw_plan_create(hw_plan** out, const hw_problem* problems,
     }
     *out = pl;
     return ok();
+}
+
+int hw_plan_create(hw_plan** out, const hw_problem* problems, const hw_buffers* buffers,
+                   int32_t n, const hw_tuning* tuning)
+{
+    return plan_create(out, problems, buffers, n, tuning, false);
+}
+
+int hw_plan_create_uniform(hw_plan** out, const hw_problem* problems,
+                           const hw_buffers* buffers, int32_t n, const hw_tuning* tuning)
+{
+    return plan_create(out, problems, buffers, n, tuning, true);
 }
 
 int hw_plan_destroy(hw_plan* plan)

@@ -48,7 +48,8 @@ struct Desc {
                            // what the time loop reads (plans): coarse level
                            // L-1, and the leaf list, leaf-level map and fill
                            // table of a step whose leaves are all finest
-    int32_t pad1;
+    int32_t uniform;       // uniform FV1 plan: every finest cell is a leaf,
+                           // no encoding, flags or traversal run
 };
 
 // Work decomposition of one launch: problem s owns workgroups

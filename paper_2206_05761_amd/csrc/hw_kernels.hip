@@ -678,6 +678,7 @@ struct Fv1Ctx {
     gp<const double> bpart;
     uint64_t step;         // index of the step being taken
     int write_skip;        // stores of unchanged dry blocks may be skipped
+    int uniform;           // uniform FV1 plan (no encoder block records)
     int L, Lg;
     int bc[4];
     double dx, dy, g, h_tol, manning_n, rain_rate;
@@ -696,6 +697,13 @@ __device__ inline void fill_rxy(double* rxy, const Desc& d, double dt)
             rxy[2 * m] = dt / ldexp(d.dx, d.L - m);
             rxy[2 * m + 1] = dt / ldexp(d.dy, d.L - m);
         }
+}
+
+// Leaves of the step: the traversal's count, or every finest cell under a
+// uniform FV1 plan.
+__device__ inline uint64_t step_leaves(const Desc& d, const hw_scalars* sc)
+{
+    return d.uniform ? (1ull << (2 * d.L)) : sc->n_leaves;
 }
 
 template <typename T>
@@ -732,7 +740,8 @@ __device__ inline void make_ctx(Fv1Ctx<T>& x, const Desc& d)
     x.t_base = d.t_base;
     x.t = sc->t;
     x.dt = sc->dt;
-    x.nl = uniform((uint32_t)sc->n_leaves);
+    x.nl = uniform((uint32_t)step_leaves(d, sc));
+    x.uniform = d.uniform;
 }
 
 // Value of the level-(L-1) cell k of one variable from its four finest
@@ -1352,7 +1361,7 @@ __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre
         for (int s = 0; s < n; ++s) {
             cpre[s] = a;
             const hw_scalars* sc = descs[s].scal;
-            const uint64_t nl = sc->n_leaves;
+            const uint64_t nl = step_leaves(descs[s], sc);
             const bool m = !sc->done;
             if (mine) mine[s] = m ? 1 : 0;
             if (finest) finest[s] = all_finest(descs[s], nl) ? 1 : 0;
@@ -1509,7 +1518,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
             c1 = uniform(cpre[s + 1]);
             fin = uniform((int)finest[s]) != 0;
         }
-        if (fin && x.L >= 5) {
+        if (fin && x.L >= 5 && !x.uniform) {
             // up to 32 of this workgroup's super-chunks at once, all of the
             // current problem
             const uint32_t lim = f.c_end < c1 ? f.c_end : c1;
@@ -1669,31 +1678,56 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
 }
 
 // Copy-down for leaves coarser than the traversal groups: every group below
-// such a leaf copies the leaf's new value from its first finest descendant.
+// such a leaf takes the leaf's new value from its first finest descendant.
+// Each lane reads its group's source; the wave then writes the cells of its
+// 64 groups with consecutive lanes on consecutive cells (the group data go
+// through the wave's slice of LDS).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fill(Launch lc)
 {
+    __shared__ uint32_t s_src[kBlock];
+    __shared__ uint64_t s_f0[kBlock];
+    __shared__ T s_val[3][kBlock];
     uint32_t lb;
     const int s = scen_of(lc, blockIdx.x, lb);
     const Desc& d = lc.descs[s];
     const hw_scalars* sc = d.scal;
     if (sc->done) return;
     if (sc->n_leaves == (1ull << (2 * d.L))) return;   // no coarser leaf at all
-    const uint32_t g = lb * kBlock + threadIdx.x;
-    if (g >= (1u << (2 * d.group_level))) return;
-    const uint32_t src = glob(d.big_src)[g];
-    if (src == kNone) return;
-    const int L = d.L;
-    const int n = level_of(src);
-    const uint64_t f0 = (uint64_t)(src - (uint32_t)level_off(n)) << (2 * (L - n));
-    const int per = 1 << (2 * (L - d.group_level));
-    const uint64_t base = (uint64_t)g * per;
+    const int L = d.L, Lg = d.group_level;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1u), w0 = tid & ~(kWave - 1u);
+    const uint32_t g = lb * kBlock + tid;
     const int o = uniform((int)sc->cur) ^ 1;
-    for (int v = 0; v < 3; ++v) {
-        const gp<T> a = glob(reinterpret_cast<T*>(d.fine[o][v]));
-        const T val = a[f0];
-        for (int q = 0; q < per; ++q)
-            if (base + q != f0) a[base + q] = val;
+    gp<T> a[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) a[v] = glob(reinterpret_cast<T*>(d.fine[o][v]));
+    uint32_t src = kNone;
+    if (g < (1u << (2 * Lg))) src = glob(d.big_src)[g];
+    uint64_t f0 = 0;
+    T val[3] = {T(0), T(0), T(0)};
+    if (src != kNone) {
+        const int n = level_of(src);
+        f0 = (uint64_t)(src - (uint32_t)level_off(n)) << (2 * (L - n));
+#pragma unroll
+        for (int v = 0; v < 3; ++v) val[v] = a[v][f0];
+    }
+    if (!wave_any(src != kNone)) return;   // no group of this wave to fill
+    s_src[tid] = src;
+    s_f0[tid] = f0;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) s_val[v][tid] = val[v];
+    __builtin_amdgcn_wave_barrier();
+    const int sh = 2 * (L - Lg);                      // log2 of cells per group
+    const uint64_t first = (uint64_t)(g - lane) << sh;  // first cell of the wave's groups
+    for (uint32_t c = lane; c < (kWave << sh); c += kWave) {
+        const uint32_t q = w0 + (c >> sh);
+        const uint32_t sq = s_src[q];
+        const uint64_t cell = first + c;
+        if (sq != kNone && cell != s_f0[q]) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) a[v][cell] = s_val[v][q];
+        }
     }
 }
 
@@ -1763,7 +1797,9 @@ __global__ __launch_bounds__(kFinalBlock) void k_finalize(const Desc* descs,
         sc->smax[1] = tot[2] > 1.0 ? tot[2] : 1.0;
         sc->smax[2] = tot[3] > 1.0 ? tot[3] : 1.0;
         sc->step += 1;
-        sc->leaf_updates += sc->n_leaves;
+        const uint64_t nl = d.uniform ? (1ull << (2 * d.L)) : sc->n_leaves;
+        sc->n_leaves = nl;
+        sc->leaf_updates += nl;
         sc->clips += (uint64_t)tot[5];
         sc->dry_stored += (uint64_t)tot[8];
         sc->dry_skipped += (uint64_t)tot[9];

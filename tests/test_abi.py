@@ -24,7 +24,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("mra_encode", "mra_flag", "mra_traverse_leaves", "fv1_step",
                      "hwfv1_run", "hwfv1_run_batch", "hw_ingest", "hw_export",
-                     "hw_plan_create", "hw_plan_destroy", "hw_last_error"):
+                     "hw_plan_create", "hw_plan_create_uniform", "hw_plan_destroy",
+                     "hw_last_error"):
         assert required in names
 
 
@@ -94,10 +95,11 @@ def test_null_and_misaligned_buffers_are_rejected_before_launch():
     assert rc == hw.HW_ECAPACITY
 
 
-def test_plan_rejects_bad_counts_without_gpu():
+@pytest.mark.parametrize("create", ["hw_plan_create", "hw_plan_create_uniform"])
+def test_plan_rejects_bad_counts_without_gpu(create):
     import paper_2206_05761_amd as hw
     h = C.c_void_p()
-    rc = hw.lib().hw_plan_create(C.byref(h), None, None, 0, None)
+    rc = getattr(hw.lib(), create)(C.byref(h), None, None, 0, None)
     assert rc == hw.HW_EINVAL
-    rc = hw.lib().hw_plan_create(C.byref(h), None, None, 65, None)
+    rc = getattr(hw.lib(), create)(C.byref(h), None, None, 65, None)
     assert rc == hw.HW_EINVAL

@@ -244,6 +244,26 @@ def dambreak_strip(L: int, h_left: float, h_right: float, x_dam: float,
                     meta=dict(h_left=h_left, h_right=h_right, x_dam=x_dam))
 
 
+def circular_dambreak_flat(L: int = 8, eps: float = 1e-3, radius: float = 2.5,
+                           t_end: float = 3.5, centre=(21.3, 20.7)) -> Workload:
+    """Circular dam break of Section 3.2: closed [-20, 20]^2 m domain (here
+    [0, 40]^2), flat frictionless bed, depth 2.5 m inside the dam and 0.5 m
+    outside, run to 3.5 s.  The paper does not print the dam's radius; 2.5 m
+    is taken.  The dam is centred at (1.3, 0.7) m from the domain centre: a
+    dam centred on the corner shared by the root's four quadrants gives the
+    root (and every coarse cell centred on it) zero details by symmetry, and
+    the tree, which stops at the first cell without a significant detail,
+    would then be the root alone."""
+    length = 40.0
+    p = base_params(L, length, eps, bc=("wall",) * 4, t_end=t_end)
+    x, y = cell_centres(L, length)
+    r = np.sqrt((x - centre[0]) ** 2 + (y - centre[1]) ** 2)
+    h = np.where(r < radius, 2.5, 0.5)
+    zero = np.zeros_like(h)
+    return Workload(f"circular_dambreak_flat_l{L}", p, h, zero, zero.copy(), zero.copy(),
+                    n_steps=100_000, meta=dict(radius=radius))
+
+
 def dry_patches(L: int, seed: int, n_rect: int = 4, n_single: int = 12,
                 inlet: bool = False, rain: float = 0.0) -> Workload:
     """Mostly dry domain over a rough bed (uniform noise of 1 m on every
