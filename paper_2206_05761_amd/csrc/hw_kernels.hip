@@ -1350,10 +1350,16 @@ __device__ inline bool all_finest(const Desc& d, uint64_t n_leaves)
     return n_leaves == (1ull << (2 * d.L));
 }
 
-// Chunk prefix over the problems that are stepping; optionally, per
-// problem, whether it steps (mine) and whether its leaves are all finest.
+// Problems a chunk schedule covers: every stepping problem, only those
+// whose leaves are all finest this step, or only the others.
+enum { kAllProblems = 0, kFinestOnly = 1, kMixedOnly = 2 };
+
+// Chunk prefix over the stepping problems of the given kind; optionally,
+// per problem, whether it steps (mine) and whether its leaves are all
+// finest.
 __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre,
-                                        uint8_t* mine = nullptr, uint8_t* finest = nullptr)
+                                        int mode = kAllProblems, uint8_t* mine = nullptr,
+                                        uint8_t* finest = nullptr)
 {
     constexpr uint32_t SC = kLeafBatch * kBlock;
     if (threadIdx.x == 0) {
@@ -1363,9 +1369,11 @@ __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre
             const hw_scalars* sc = descs[s].scal;
             const uint64_t nl = step_leaves(descs[s], sc);
             const bool m = !sc->done;
+            const bool fin = all_finest(descs[s], nl);
             if (mine) mine[s] = m ? 1 : 0;
-            if (finest) finest[s] = all_finest(descs[s], nl) ? 1 : 0;
-            a += m ? ((uint32_t)nl + SC - 1) / SC : 0u;
+            if (finest) finest[s] = fin ? 1 : 0;
+            const bool take = m && (mode == kAllProblems || (mode == kFinestOnly) == fin);
+            a += take ? ((uint32_t)nl + SC - 1) / SC : 0u;
         }
         cpre[n] = a;
     }
@@ -1494,84 +1502,86 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
     __shared__ uint8_t finest[kMaxScen];
     __shared__ uint32_t slist[kBlock];
     __shared__ uint32_t scount;
-    const Fv1Sched f = fv1_schedule(descs, n, cpre, mine, finest);
-    // no problem is stepping: nothing to update and no records to write
-    // (finalize reads records of problems that are stepping only)
-    if (uniform(cpre[n]) == 0u) return;
     Acc acc;
     acc_reset(acc);
-    int cs = -1;
     Fv1Ctx<T> x;
-    uint32_t c0 = 0, c1 = 0;
     gp<uint8_t> wetb = gp<uint8_t>(nullptr);
-    bool fin = false;
-    for (uint32_t ch = f.c_begin; ch < f.c_end; ch += f.g8) {
-        if (cs < 0 || ch >= c1) {
-            int s = cs < 0 ? 0 : cs;
-            while (cpre[s + 1] <= ch) ++s;
-            s = uniform(s);
-            if (cs >= 0) acc_flush(acc, red, rec[cs]);
-            cs = s;
-            make_ctx<T>(x, descs[s]);
-            wetb = glob(descs[s].wet);
-            c0 = uniform(cpre[s]);
-            c1 = uniform(cpre[s + 1]);
-            fin = uniform((int)finest[s]) != 0;
-        }
-        if (fin && x.L >= 5 && !x.uniform) {
-            // up to 32 of this workgroup's super-chunks at once, all of the
-            // current problem
-            const uint32_t lim = f.c_end < c1 ? f.c_end : c1;
-            uint32_t cnt = (lim - ch + f.g8 - 1u) / f.g8;
-            cnt = cnt < 32u ? cnt : 32u;
-            light_blocks<T>(x, wetb, ch - c0, f.g8, cnt, acc, slist, scount);
-            ch += (cnt - 1u) * f.g8;
-            continue;
-        }
-        const uint32_t sc = ch - c0;
-        const uint32_t base = sc * SC;
-        LightBatch<T> b;
-        uint32_t bits = 0;
-        if (fin) {
-            light_probe_finest<T>(x, base, b);
-            // every full wave is one aligned 64-cell block of finest leaves
-            const double area = x.dx * x.dy;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = base + (uint32_t)u * kBlock + tid < x.nl;
-                const bool wet = x.rain_rate != 0.0 || wave_any(ok && !b.dry[u]);
-                const bool skip = light_history_block<T>(x, !wave_any(!ok), b.c[u], !wet, b.e[u]);
-                if (wet) {
-                    bits |= 1u << u;
-                } else if (ok) {
-                    if (!skip) {
-                        x.fout[0][b.c[u]] = b.h[u];
-                        x.fout[1][b.c[u]] = T(0);
-                        x.fout[2][b.c[u]] = T(0);
+    // The problems whose leaves are all finest, then the others, each kind
+    // spread over every workgroup (and so over every XCD) on its own: the
+    // two kinds cost very differently per chunk.
+    for (int kind = 0; kind < 2; ++kind) {
+        const bool fin = kind == 0;
+        const Fv1Sched f =
+            fv1_schedule(descs, n, cpre, fin ? kFinestOnly : kMixedOnly, mine, finest);
+        int cs = -1;
+        uint32_t c0 = 0, c1 = 0;
+        for (uint32_t ch = f.c_begin; ch < f.c_end; ch += f.g8) {
+            if (cs < 0 || ch >= c1) {
+                int s = cs < 0 ? 0 : cs;
+                while (cpre[s + 1] <= ch) ++s;
+                s = uniform(s);
+                if (cs >= 0) acc_flush(acc, red, rec[cs]);
+                cs = s;
+                make_ctx<T>(x, descs[s]);
+                wetb = glob(descs[s].wet);
+                c0 = uniform(cpre[s]);
+                c1 = uniform(cpre[s + 1]);
+            }
+            if (fin && x.L >= 5 && !x.uniform) {
+                // up to 32 of this workgroup's super-chunks at once, all of the
+                // current problem
+                const uint32_t lim = f.c_end < c1 ? f.c_end : c1;
+                uint32_t cnt = (lim - ch + f.g8 - 1u) / f.g8;
+                cnt = cnt < 32u ? cnt : 32u;
+                light_blocks<T>(x, wetb, ch - c0, f.g8, cnt, acc, slist, scount);
+                ch += (cnt - 1u) * f.g8;
+                continue;
+            }
+            const uint32_t sc = ch - c0;
+            const uint32_t base = sc * SC;
+            LightBatch<T> b;
+            uint32_t bits = 0;
+            if (fin) {
+                light_probe_finest<T>(x, base, b);
+                // every full wave is one aligned 64-cell block of finest leaves
+                const double area = x.dx * x.dy;
+    #pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool ok = base + (uint32_t)u * kBlock + tid < x.nl;
+                    const bool wet = x.rain_rate != 0.0 || wave_any(ok && !b.dry[u]);
+                    const bool skip = light_history_block<T>(x, !wave_any(!ok), b.c[u], !wet, b.e[u]);
+                    if (wet) {
+                        bits |= 1u << u;
+                    } else if (ok) {
+                        if (!skip) {
+                            x.fout[0][b.c[u]] = b.h[u];
+                            x.fout[1][b.c[u]] = T(0);
+                            x.fout[2][b.c[u]] = T(0);
+                        }
+                        acc_max(acc, 1, fabs((double)b.h[u]));
+                        acc.v[4] += (double)b.h[u] * area;
+                        acc.v[8] += skip ? 0.0 : 1.0;
+                        acc.v[9] += skip ? 1.0 : 0.0;
                     }
-                    acc_max(acc, 1, fabs((double)b.h[u]));
-                    acc.v[4] += (double)b.h[u] * area;
-                    acc.v[8] += skip ? 0.0 : 1.0;
-                    acc.v[9] += skip ? 1.0 : 0.0;
+                }
+            } else {
+                uint32_t idx[U];
+                light_indices<T>(x, base, idx);
+                light_probe<T>(x, idx, b);
+    #pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool ok = base + (uint32_t)u * kBlock + tid < x.nl;
+                    const bool wet = x.rain_rate != 0.0 || wave_any(ok && !b.dry[u]);
+                    const bool skip = light_history<T>(x, ok, b.m[u], b.c[u], !wet, b.e[u]);
+                    if (wet) bits |= 1u << u;
+                    else if (ok) fv1_dry_write<T>(x, b.m[u], b.c[u], b.h[u], acc, !skip);
                 }
             }
-        } else {
-            uint32_t idx[U];
-            light_indices<T>(x, base, idx);
-            light_probe<T>(x, idx, b);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = base + (uint32_t)u * kBlock + tid < x.nl;
-                const bool wet = x.rain_rate != 0.0 || wave_any(ok && !b.dry[u]);
-                const bool skip = light_history<T>(x, ok, b.m[u], b.c[u], !wet, b.e[u]);
-                if (wet) bits |= 1u << u;
-                else if (ok) fv1_dry_write<T>(x, b.m[u], b.c[u], b.h[u], acc, !skip);
-            }
+            if ((tid & (kWave - 1)) == 0) wetb[4ull * sc + wid] = (uint8_t)bits;
         }
-        if ((tid & (kWave - 1)) == 0) wetb[4ull * sc + wid] = (uint8_t)bits;
+        if (cs >= 0) acc_flush(acc, red, rec[cs]);
+        __syncthreads();   // cpre is rewritten by the next kind's schedule
     }
-    if (cs >= 0) acc_flush(acc, red, rec[cs]);
-    __syncthreads();
     // records of the problems that are stepping
     for (int q = tid; q < n * kPartial; q += kBlock) {
         const int s = q / kPartial;
