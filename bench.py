@@ -321,6 +321,65 @@ def bench_speedup(hw, levels=(8, 9, 10, 11, 12), epss=(1e-4, 1e-3, 1e-2)):
             "precision": "fp64", "unit": "ms to t_end (HIP events)", "rows": rows}
 
 
+def run_history_ms(hw, w, uniform, chunk):
+    """(t, elapsed ms) after every `chunk` steps of a FP64 run from the
+    initial state to t_end (HIP events; the plan is captured beforehand)."""
+    import numpy as np
+    import torch
+    sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision="fp64")
+    plan = hw.Plan([sim.problem], [sim.buffers], uniform=uniform)
+    hw.hwfv1_run(sim.problem, sim.buffers, 1, plan=plan, stats=False)
+    dev = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1), device="cuda")
+           for a in (w.h, w.qx, w.qy, w.z)]
+    hw.hw_ingest(sim.problem, sim.buffers, *dev)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hist = [(0.0, 0.0)]
+    while True:
+        hw.hwfv1_run(sim.problem, sim.buffers, chunk, plan=plan, stats=False)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e1.record()
+        s = sim.scalars()
+        hist.append((s["t"], e0.elapsed_time(e1)))
+        if s["done"]:
+            break
+    steps = sim.scalars()["step"]
+    plan.close()
+    sim.close()
+    return hist, steps
+
+
+def bench_pseudo2d(hw, levels=(8, 9, 10, 11), epss=(1e-4, 1e-3, 1e-2), window=2.5, t_end=40.0):
+    """Speed-up of HWFV1 over uniform FV1 through the 40 s pseudo-2D dam
+    break, per window of simulated time (the paper's Fig. 14)."""
+    import numpy as np
+    import workloads as W
+    marks = np.arange(0.0, t_end + 1e-9, window)
+
+    def at(hist, t):
+        ts, ms = zip(*hist)
+        return float(np.interp(t, ts, ms))
+
+    rows = []
+    for L in levels:
+        chunk = 32 << (L - 8)
+        uh, un = run_history_ms(hw, W.pseudo2d_dambreak(L, t_end=t_end), True, chunk)
+        u = [at(uh, t) for t in marks]
+        for eps in epss:
+            hh, hn = run_history_ms(hw, W.pseudo2d_dambreak(L, eps, t_end=t_end), False, chunk)
+            h = [at(hh, t) for t in marks]
+            win = [round((u[i + 1] - u[i]) / (h[i + 1] - h[i]), 3) for i in range(len(marks) - 1)]
+            rows.append({"L": L, "eps": eps, "steps": hn, "hwfv1_ms": round(h[-1], 2),
+                         "uniform_fv1_ms": round(u[-1], 2), "speedup": round(u[-1] / h[-1], 3),
+                         "window_speedup": win})
+            log(f"[bench] pseudo-2D L={L} eps={eps}: {hn} steps, HWFV1 {h[-1]:.0f} ms, "
+                f"uniform {u[-1]:.0f} ms, x{u[-1] / h[-1]:.2f}; per {window} s: {win}")
+    return {"workload": "pseudo2d_dambreak (flat, frictionless, 6 m | 2 m at x = 10 m, "
+                        "50 m square, open ends, to t = 40 s)",
+            "precision": "fp64", "window_s": window, "rows": rows}
+
+
 def cpu_baseline(w, n_steps):
     import oracle as O
     log(f"[bench] cpu oracle: {n_steps} steps of {w.name}")
@@ -458,6 +517,7 @@ def main():
         ru["sim"].close()
         del ru
         line["speedup_series"] = bench_speedup(hw)
+        line["speedup_pseudo2d"] = bench_pseudo2d(hw)
     if not args.no_fp32:
         r32 = time_single(hw, w, "fp32_bulk", args.steps, args.warmup, args.prof_steps,
                           tuning)

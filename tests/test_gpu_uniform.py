@@ -163,3 +163,28 @@ def test_circular_dambreak_flat_full_run_matches_oracle(hw):
     ho, qxo, qyo = ou.fine()
     assert max(_max_abs(h, ho), _max_abs(qx, qxo), _max_abs(qy, qyo)) <= TOL
     u.close()
+
+
+def test_pseudo2d_dambreak_matches_oracle(hw):
+    """The pseudo-2D dam break of the transient speed-up series to 2.5 s at
+    L = 7: HWFV1 and the uniform plan against the oracle."""
+    w = W.pseudo2d_dambreak(7, t_end=2.5)
+    sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z)
+    st = sim.run(100_000)
+    o = O.Oracle(w.params, w.h, w.qx, w.qy, w.z)
+    n = o.run(100_000)
+    so = o.scalars()
+    log("  pseudo-2D steps", st["steps"], n, "leaves", so["n_leaves"], "of", 4 ** w.L)
+    assert st["steps"] == n and st["t"] == so["t"] == 2.5
+    h, qx, qy = sim.export()
+    ho, qxo, qyo = o.fine()
+    assert max(_max_abs(h, ho), _max_abs(qx, qxo), _max_abs(qy, qyo)) <= TOL
+    assert np.array_equal(sim.buffers.leaf_list(), o.leaves())
+    sim.close()
+    u, su = _uniform_run(hw, w, 100_000)
+    ou, nu = _oracle_uniform(w, 100_000)
+    assert su["steps"] == nu
+    h, qx, qy = u.export()
+    ho, qxo, qyo = ou.fine()
+    assert max(_max_abs(h, ho), _max_abs(qx, qxo), _max_abs(qy, qyo)) <= TOL
+    u.close()

@@ -264,6 +264,18 @@ def circular_dambreak_flat(L: int = 8, eps: float = 1e-3, radius: float = 2.5,
                     n_steps=100_000, meta=dict(radius=radius))
 
 
+def pseudo2d_dambreak(L: int = 8, eps: float = 1e-3, t_end: float = 40.0) -> Workload:
+    """Pseudo-2D dam break of Section 3.2: flat frictionless bed, 6 m of
+    water upstream of a dam at x = 10 m and 2 m downstream, open ends, run
+    to 40 s (shock and rarefaction leave the domain; the flow then smooths).
+    The paper's domain is 50 m x 25 m; the flow does not depend on y, so the
+    square 50 m x 50 m domain (walls along the flow) carries the same
+    solution on every row."""
+    w = dambreak_strip(L, 6.0, 2.0, 10.0, 50.0, eps, t_end, axis="x")
+    w.name = f"pseudo2d_dambreak_l{L}"
+    return w
+
+
 def dry_patches(L: int, seed: int, n_rect: int = 4, n_single: int = 12,
                 inlet: bool = False, rain: float = 0.0) -> Workload:
     """Mostly dry domain over a rough bed (uniform noise of 1 m on every
