@@ -419,8 +419,8 @@ def main():
                          "times (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the ensemble and the Morton-subtree sharding are single-GPU); "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(Morton-subtree sharding is a design, not an implementation); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
