@@ -162,10 +162,13 @@ typedef struct hw_scalars {
  *               (N-1)/3 + m for m = 0..N-1)
  *   scal        one hw_scalars record
  *   work        scratch of hw_workspace_bytes() bytes, private to the
- *               library; between mra_traverse_leaves and fv1_step it carries
- *               the traversal's fill table and the per-finest-cell leaf
- *               level map (N bytes) that the FV1 neighbour lookup reads;
- *               across steps it keeps the FV1 write history (hw_forget)
+ *               library; between mra_encode and fv1_step it carries the
+ *               encoder's per-64-cell block records (dry flags, mass, max
+ *               depth) that the FV1 dry pass reads; between
+ *               mra_traverse_leaves and fv1_step the traversal's fill table
+ *               and the per-finest-cell leaf level map (N bytes) that the
+ *               FV1 neighbour lookup reads; across steps it keeps the FV1
+ *               write history (hw_forget)
  */
 typedef struct hw_buffers {
     void* fine[2][3];

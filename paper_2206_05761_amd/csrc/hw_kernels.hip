@@ -7,15 +7,21 @@
 //   k_regularise  refine the face neighbours of significant cells.
 //   k_traverse    per-group walk down the significance tree (Algorithm 5) and
 //                 ordered compaction of the leaves (count, scan, emit).
-//   k_fv1         FV1 update of every leaf with same-level neighbours (Fig. 3),
-//                 write-back to the finest descendants, partial reductions.
+//   k_fv1_light   FV1, every leaf's dry test: groups of 64 leaves that are
+//                 dry with dry neighbours are finished there ((h, 0, 0)), the
+//                 others marked for the heavy kernel.
+//   k_fv1_heavy   FV1 update of the marked leaves with same-level neighbours
+//                 (Fig. 3); both write back to the finest descendants and
+//                 leave partial reductions.
 //   k_fill        copy-down of leaves coarser than a traversal group.
 //   k_finalize    t += dt, CFL timestep, s_max, mass (minimum reduction of
 //                 Section 2.2.3), flip of the finest buffer set.
 //
-// Floating-point expressions are written in the same order as the method's
-// definition so that, compiled without contraction, the FP64 path performs
-// the same IEEE operations in the same order for every cell value.
+// The encoding and the significance test perform, compiled without
+// contraction, the same IEEE operations in the same order as the method's
+// definition (their FP64 results are bit-identical to it).  The FV1 update
+// takes one reciprocal where the definition divides several times by the
+// same quantity, so it differs from it by rounding only.
 #include "hw_device.h"
 
 #include <math.h>
