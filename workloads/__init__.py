@@ -276,6 +276,20 @@ def pseudo2d_dambreak(L: int = 8, eps: float = 1e-3, t_end: float = 40.0) -> Wor
     return w
 
 
+def pseudo2d_channel(L: int = 8, eps: float = 1e-3, t_end: float = 40.0) -> Workload:
+    """The pseudo-2D dam break on the paper's 50 m x 25 m domain: the
+    channel fills the lower half of the 50 m square grid (rows along y),
+    the upper half is dry ground 1000 m above the water (a closed edge in
+    the hydrostatic reconstruction)."""
+    w = pseudo2d_dambreak(L, eps, t_end)
+    n = 1 << L
+    w.h[n // 2:, :] = 0.0
+    w.z[n // 2:, :] = 1000.0
+    w.name = f"pseudo2d_channel_l{L}"
+    w.meta = dict(w.meta, channel_rows=n // 2)
+    return w
+
+
 def dry_patches(L: int, seed: int, n_rect: int = 4, n_single: int = 12,
                 inlet: bool = False, rain: float = 0.0) -> Workload:
     """Mostly dry domain over a rough bed (uniform noise of 1 m on every
