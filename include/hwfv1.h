@@ -139,7 +139,10 @@ typedef struct hw_scalars {
     uint32_t cur;        /* finest set (0 or 1) holding the current state  */
     uint32_t done;       /* 1 once t >= t_end                              */
     uint32_t nonfinite;  /* 1 if a non-finite value was produced           */
-    uint32_t pad;
+    uint32_t map_step;   /* step + 1 (low 32 bits) of the step whose
+                            traversal last wrote the leaf-level map, 0 after
+                            hw_ingest; equal to step when the map describes
+                            the tree whose copy-down made the current set  */
 } hw_scalars;
 
 /*
@@ -194,6 +197,12 @@ typedef struct hw_tuning {
                                         the dry case left unchanged at the
                                         two previous steps (see hw_forget);
                                         0: store every leaf every step     */
+    int32_t encode_skip;             /* 1: the first encoding pass loads one
+                                        cell of a wave's span of finest
+                                        cells when the previous step's tree
+                                        has one leaf over the whole span
+                                        (the copy-down made them equal);
+                                        0: load every finest cell          */
 } hw_tuning;
 
 typedef struct hw_plan hw_plan;
@@ -362,8 +371,11 @@ int hw_plan_profile(hw_plan* plan, int64_t steps, double* ms_out,
  * depths <= h_tol, no inflow, no rain) has finished at the two previous
  * steps, because the set being written then already holds the result; it
  * learns this from a per-block record of those steps in `work`.  hw_ingest
- * clears the record.  Call this after writing fine[][] or scal by any other
- * means (e.g. restoring a saved state) before the next step.  Errors:
+ * clears the record.  It also sets hw_scalars.map_step to 0, so the next
+ * encoding loads every finest cell instead of one per span below a coarser
+ * leaf of the previous tree.  Call this after writing fine[][] or scal by
+ * any other means (e.g. restoring a saved state) before the next step.
+ * Errors:
  * HW_EINVAL for a bad problem or buffers, HW_EHIP on launch failure.
  */
 int hw_forget(const hw_problem* p, const hw_buffers* b, hipStream_t stream);

@@ -52,7 +52,7 @@ class HwScalars(C.Structure):
         ("leaf_updates", C.c_uint64), ("clips", C.c_uint64),
         ("dry_stored", C.c_uint64), ("dry_skipped", C.c_uint64),
         ("cur", C.c_uint32), ("done", C.c_uint32), ("nonfinite", C.c_uint32),
-        ("pad", C.c_uint32),
+        ("map_step", C.c_uint32),
     ]
 
 
@@ -68,7 +68,7 @@ class HwBuffers(C.Structure):
 class HwTuning(C.Structure):
     _fields_ = [("encode_cells_per_thread", C.c_int32),
                 ("fv1_block", C.c_int32), ("fv1_grid", C.c_int32),
-                ("fv1_write_skip", C.c_int32)]
+                ("fv1_write_skip", C.c_int32), ("encode_skip", C.c_int32)]
 
 
 class HwStats(C.Structure):
@@ -222,7 +222,7 @@ class Buffers:
     def scalars(self) -> dict:
         raw = self.scal.cpu().numpy().tobytes()
         s = HwScalars.from_buffer_copy(raw)
-        out = {k: getattr(s, k) for k, _ in HwScalars._fields_ if k not in ("smax", "acc", "pad")}
+        out = {k: getattr(s, k) for k, _ in HwScalars._fields_ if k not in ("smax", "acc", "map_step")}
         out["smax"] = list(s.smax)
         return out
 
@@ -319,7 +319,8 @@ class Plan:
             tu = HwTuning(int(tuning.get("encode_cells_per_thread", 0)),
                           int(tuning.get("fv1_block", 0)),
                           int(tuning.get("fv1_grid", 0)),
-                          int(tuning.get("fv1_write_skip", 1)))
+                          int(tuning.get("fv1_write_skip", 1)),
+                          int(tuning.get("encode_skip", 1)))
         h = C.c_void_p()
         create = lib().hw_plan_create_uniform if uniform else lib().hw_plan_create
         _check(create(C.byref(h), self._probs, self._bufs, n,

@@ -495,6 +495,7 @@ void hw_default_tuning(const hw_problem* p, hw_tuning* out)
     out->fv1_block = hw::kBlock;
     out->fv1_grid = 0;
     out->fv1_write_skip = 1;
+    out->encode_skip = 1;
 }
 
 int hw_ingest(const hw_problem* p, const hw_buffers* b, const double* h,
@@ -660,6 +661,11 @@ static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffe
             return fail(HW_EINVAL, "fv1_write_skip must be 0 or 1");
         }
         tu.fv1_write_skip = tuning->fv1_write_skip;
+        if (tuning->encode_skip != 0 && tuning->encode_skip != 1) {
+            delete pl;
+            return fail(HW_EINVAL, "encode_skip must be 0 or 1");
+        }
+        tu.encode_skip = tuning->encode_skip;
     }
     pl->cp = tu.encode_cells_per_thread == 16 ? 2 : 1;
     pl->write_skip = tu.fv1_write_skip;
@@ -730,6 +736,7 @@ static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffe
             &problems[i], &buffers[i],
             pl->d_partials + 2 * (size_t)i * pl->fv1_grid * hw::kPartial));
         pl->host_desc.back().write_skip = pl->write_skip;
+        pl->host_desc.back().encode_skip = tu.encode_skip;
         pl->host_desc.back().full_outputs = 0;
         pl->host_desc.back().uniform = uniform ? 1 : 0;
     }

@@ -50,6 +50,8 @@ struct Desc {
                            // table of a step whose leaves are all finest
     int32_t uniform;       // uniform FV1 plan: every finest cell is a leaf,
                            // no encoding, flags or traversal run
+    int32_t encode_skip;   // the first encoding pass may load one cell per
+                           // wave span below a coarser leaf (plans only)
 };
 
 // Work decomposition of one launch: problem s owns workgroups

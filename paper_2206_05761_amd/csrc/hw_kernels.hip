@@ -142,6 +142,9 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
 #pragma unroll
     for (int v = 0; v < 4; ++v) smax_all[v] = sc->smax[v];
     const double t_now = sc->t;
+    const uint64_t step = sc->step;
+    const uint32_t map_step = sc->map_step;
+    const uint64_t n_leaves = sc->n_leaves;
     if (FLOW && done) return;
     const int L = d.L;
     const int n_in = L - pass * tl;
@@ -299,12 +302,28 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
         }
     };
 
+    // Below a leaf of the previous step's tree every finest cell holds the
+    // leaf's value (the copy-down of the FV1 update).  When the leaf-level
+    // map still describes that tree (it was written in the step that made
+    // the current set), a wave whose span of 64 * cells finest cells lies
+    // inside one leaf loads the span's first `cells` cells on every lane:
+    // the values are the same bits, so everything computed from them is
+    // unchanged, and the span costs one or two cache lines per variable
+    // instead of all its cells.
+    bool span_skip = FLOW && pass == 0 && d.encode_skip && lv - cp >= 3 && step > 0 &&
+                     map_step == (uint32_t)step && n_leaves < (1ull << (2 * L));
     double p[NV];
     if ((uint32_t)tid < M) {
         const uint64_t tile_in = (uint64_t)b << (2 * lv);
+        uint64_t own = tile_in + (uint64_t)cells * tid;
+        if (span_skip) {
+            const uint64_t wf = tile_in + (uint64_t)cells * uniform((uint32_t)(tid & ~(kWave - 1)));
+            const int span_level = L - (cells == 4 ? 4 : 5);
+            if ((int)glob(static_cast<const uint8_t*>(d.lmap))[wf] <= span_level) own = wf;
+        }
         // All child loads are issued before any store of this thread.
         if (CP == 1 || cp == 1) {
-            const uint64_t base = tile_in + 4ull * tid;
+            const uint64_t base = own;
             double ch[NV][4];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -316,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
             if (blocks) block_test(ch[0]);
             emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + tid, ch, p, zr[0]);
         } else {
-            const uint64_t base = tile_in + 16ull * tid;
+            const uint64_t base = own;
             double ch[4][NV][4];
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq)
@@ -623,6 +642,8 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
         glob(d.big_src)[g] = big;
         write_level_map(d, g, lvl);
     }
+    // the map now describes this step's tree
+    if (lb == 0 && threadIdx.x == 0) glob(d.scal)->map_step = (uint32_t)(d.scal->step + 1);
     __syncthreads();
     const gp<uint32_t> out = glob(d.leaves) + glob(d.tcount)[lb];
     for (uint32_t i = threadIdx.x; i < total; i += kBlock) out[i] = stage[i];
@@ -1920,7 +1941,7 @@ __global__ __launch_bounds__(kBlock) void k_ingest_final(const Desc* dd, int gri
         sc->cur = 0;
         sc->done = (0.0 < d.t_end) ? 0u : 1u;
         sc->nonfinite = tot[6] > 0.0 ? 2u : 0u;
-        sc->pad = 0;
+        sc->map_step = 0;
     }
 }
 
@@ -2080,6 +2101,7 @@ __global__ __launch_bounds__(kBlock) void k_forget(const Desc* dd)
 {
     const gp<uint64_t> hist = glob(dd->hist);
     const uint32_t n = dd->nhist;
+    if (blockIdx.x == 0 && threadIdx.x == 0) glob(dd->scal)->map_step = 0u;
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
         hist[i] = 0ull;
 }
