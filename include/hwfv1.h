@@ -149,7 +149,8 @@ typedef struct hw_scalars {
  * Buffers of one problem (all device memory, caller-owned):
  *   fine[2][3]  two sets of finest h, qx, qy, N entries each, flow type;
  *               hw_scalars.cur names the set holding the current state and
- *               fv1_step writes the other one and flips cur
+ *               fv1_step writes the other one and flips cur; after a plan
+ *               call only fine[cur] is guaranteed complete
  *   coarse[3]   levels 0..L-1 of h, qx, qy, (N-1)/3 entries, flow type;
  *               mra_encode writes every level, the time loop (hwfv1_run,
  *               hwfv1_run_batch, hw_plan_profile) levels 0..L-2 only: the
@@ -203,6 +204,14 @@ typedef struct hw_tuning {
                                         has one leaf over the whole span
                                         (the copy-down made them equal);
                                         0: load every finest cell          */
+    int32_t fill_skip;               /* 1 (with encode_skip): the copy-down
+                                        writes, in each span of 1024 finest
+                                        cells below one leaf of level
+                                        <= L-5, only the cells the next
+                                        encoding reads; the span is made
+                                        whole when a later tree refines it
+                                        and at the end of every run call;
+                                        0: write every cell every step     */
 } hw_tuning;
 
 typedef struct hw_plan hw_plan;
@@ -305,7 +314,10 @@ int fv1_step(const hw_problem* p, const hw_buffers* b, hipStream_t stream);
  * captured once into a HIP graph held by the plan and replayed; t, dt and
  * the leaf count stay on the device.  plan may be NULL (a temporary plan is
  * made and destroyed).  stats may be NULL; when given, the call
- * synchronises the stream and fills it.
+ * synchronises the stream and fills it.  Between the steps of one call the
+ * copy-down may leave spans below coarse leaves incomplete
+ * (hw_tuning.fill_skip); the call ends by completing them, so afterwards
+ * fine[cur] holds the whole state (the other set may not).
  */
 int hwfv1_run(const hw_problem* p, const hw_buffers* b, hw_plan* plan,
               int64_t max_steps, hw_stats* stats, hipStream_t stream);
@@ -351,7 +363,8 @@ int hwfv1_run_batch(hw_plan* plan, int64_t max_steps, hw_stats* stats,
  * the same kernels as a replay, with HIP events recorded on `stream` around
  * each phase.  ms_out[HW_NPHASE] receives the total milliseconds per phase
  * (HW_PH_*), summed over the steps.  Synchronises the stream.  For tools
- * that need per-kernel averages (roofline reports).
+ * that need per-kernel averages (roofline reports).  Like hwfv1_run it
+ * ends by completing fine[cur] (not timed).
  */
 enum {
     HW_PH_ENCODE = 0,     /* all encoding passes (with flags)            */

@@ -36,6 +36,7 @@ hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
 hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, hipStream_t s);
 hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t s);
 hipError_t launch_forget(const Desc* dd, uint64_t nhist, hipStream_t s);
+hipError_t launch_densify(int prec, const Desc* dd, int L, hipStream_t s);
 }  // namespace hw
 
 using hw::Desc;
@@ -433,6 +434,18 @@ int plan_replay(hw_plan* pl, int64_t steps, hipStream_t s, bool stop_when_done,
     return HW_OK;
 }
 
+// Complete the spans the last copy-down of each problem left stale (a
+// no-op for problems and plans that leave none).
+hipError_t plan_densify(hw_plan* pl, hipStream_t s)
+{
+    for (int i = 0; i < pl->n; ++i) {
+        if (!hw::sparse_fine(pl->host_desc[i])) continue;
+        hipError_t e = hw::launch_densify(pl->precision, pl->d_desc + i, pl->problems[i].L, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 int fill_stats(hw_plan* pl, const std::vector<uint64_t>& step0, hw_stats* stats,
                double wall, hipStream_t s)
 {
@@ -496,6 +509,7 @@ void hw_default_tuning(const hw_problem* p, hw_tuning* out)
     out->fv1_grid = 0;
     out->fv1_write_skip = 1;
     out->encode_skip = 1;
+    out->fill_skip = 1;
 }
 
 int hw_ingest(const hw_problem* p, const hw_buffers* b, const double* h,
@@ -666,6 +680,11 @@ static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffe
             return fail(HW_EINVAL, "encode_skip must be 0 or 1");
         }
         tu.encode_skip = tuning->encode_skip;
+        if (tuning->fill_skip != 0 && tuning->fill_skip != 1) {
+            delete pl;
+            return fail(HW_EINVAL, "fill_skip must be 0 or 1");
+        }
+        tu.fill_skip = tuning->fill_skip;
     }
     pl->cp = tu.encode_cells_per_thread == 16 ? 2 : 1;
     pl->write_skip = tu.fv1_write_skip;
@@ -737,6 +756,7 @@ static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffe
             pl->d_partials + 2 * (size_t)i * pl->fv1_grid * hw::kPartial));
         pl->host_desc.back().write_skip = pl->write_skip;
         pl->host_desc.back().encode_skip = tu.encode_skip;
+        pl->host_desc.back().fill_skip = tu.fill_skip;
         pl->host_desc.back().full_outputs = 0;
         pl->host_desc.back().uniform = uniform ? 1 : 0;
     }
@@ -796,6 +816,8 @@ static int run_plan(hw_plan* pl, int64_t max_steps, hw_stats* stats, hipStream_t
     for (int i = 0; i < pl->n; ++i) finite_end |= std::isfinite(pl->problems[i].t_end);
     rc = plan_replay(pl, max_steps, stream, finite_end, nullptr);
     if (rc) return rc;
+    e = plan_densify(pl, stream);
+    if (e != hipSuccess) return hip_fail(e, "densify launch");
     if (stats) {
         e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "stream synchronize");
@@ -865,6 +887,10 @@ int hw_plan_profile(hw_plan* plan, int64_t steps, double* ms_out, hipStream_t st
             ms_out[ph] += ms;
         }
         if (e != hipSuccess) rc = hip_fail(e, "phase timing");
+    }
+    if (rc == HW_OK) {
+        hipError_t e = plan_densify(plan, stream);
+        if (e != hipSuccess) rc = hip_fail(e, "densify launch");
     }
     for (int k = 0; k <= HW_NPHASE; ++k) (void)hipEventDestroy(ev[k]);
     return rc ? rc : ok();

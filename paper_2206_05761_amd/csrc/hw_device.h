@@ -52,7 +52,23 @@ struct Desc {
                            // no encoding, flags or traversal run
     int32_t encode_skip;   // the first encoding pass may load one cell per
                            // wave span below a coarser leaf (plans only)
+    int32_t fill_skip;     // the copy-down may leave spans below a coarser
+                           // leaf incomplete (plans only, with encode_skip)
 };
+
+// Tree-sparse finest set (plans, L >= 7).  A span is an aligned run of 1024
+// finest cells (one level L-5 cell; 64 traversal groups of 16 cells, one
+// wave of the traversal and of the copy-down).  When one leaf at level
+// <= L-5 covers a span, the copy-down writes only its groups 0, 16, 32 and
+// 48 (the cells the first encoding pass reads there, for either tile); the
+// other cells keep older values.  Such a stale span is made whole again
+// from its first cell when the next tree no longer covers it (traversal
+// emit pass), and at the end of every run call (k_densify), so outside a
+// run the current set is complete.
+__host__ __device__ inline bool sparse_fine(const Desc& d)
+{
+    return d.fill_skip && d.encode_skip && !d.full_outputs && !d.uniform && d.L >= 7;
+}
 
 // Work decomposition of one launch: problem s owns workgroups
 // [prefix[s], prefix[s+1]).  prefix == nullptr means one problem that owns

@@ -310,8 +310,8 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     // the values are the same bits, so everything computed from them is
     // unchanged, and the span costs one or two cache lines per variable
     // instead of all its cells.
-    bool span_skip = FLOW && pass == 0 && d.encode_skip && lv - cp >= 3 && step > 0 &&
-                     map_step == (uint32_t)step && n_leaves < (1ull << (2 * L));
+    const bool span_skip = FLOW && pass == 0 && d.encode_skip && lv - cp >= 3 && step > 0 &&
+                           map_step == (uint32_t)step && n_leaves < (1ull << (2 * L));
     double p[NV];
     if ((uint32_t)tid < M) {
         const uint64_t tile_in = (uint64_t)b << (2 * lv);
@@ -595,6 +595,37 @@ __device__ inline void write_level_map(const Desc& d, uint32_t g, const uint32_t
     }
 }
 
+// cnt (1, or a multiple of 4) equal values from p on, with vector stores.
+template <typename T>
+__device__ inline void store_run(gp<T> p, uint32_t cnt, T v)
+{
+    if (cnt == 1) {
+        p[0] = v;
+        return;
+    }
+    if (sizeof(T) == 8) {
+        const vd2 w = {(double)v, (double)v};
+        for (uint32_t q = 0; q < cnt; q += 2) *reinterpret_cast<gp<vd2>>(p + q) = w;
+    } else {
+        const vf4 w = {(float)v, (float)v, (float)v, (float)v};
+        for (uint32_t q = 0; q < cnt; q += 4) *reinterpret_cast<gp<vf4>>(p + q) = w;
+    }
+}
+
+// One wave writes the first cell's value of every variable to all 1024
+// cells of the span starting at first, in finest set cur.
+template <typename T>
+__device__ inline void fill_span(const Desc& d, int cur, uint64_t first)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1u);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const gp<T> f = glob(reinterpret_cast<T*>(d.fine[cur][v]));
+        const T val = f[first];
+        store_run<T>(f + first + 16u * lane, 16u, val);
+    }
+}
+
 // Count pass (EMIT = false): walk, store the walk code of each group and
 // the workgroup's leaf count.  Emit pass: rebuild the leaves from the codes,
 // place them at the workgroup offset plus the in-workgroup prefix, and write
@@ -606,10 +637,16 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     uint32_t lb;
     const int s = scen_of(lc, blockIdx.x, lb);
     const Desc& d = lc.descs[s];
-    if (d.scal->done) return;
+    const hw_scalars* sc = d.scal;
+    if (sc->done) return;
+    // Spans of the current set may be stale when the previous step's tree
+    // covered them (the map still describes that tree: it was written in
+    // the step that made the set).
+    const bool stale = EMIT && sparse_fine(d) && sc->step > 0 &&
+                       sc->map_step == (uint32_t)sc->step;
     // In the time loop a step whose leaves are all finest needs no list,
     // map or fill table: the FV1 kernels take that case from n_leaves.
-    if (EMIT && !d.full_outputs && d.scal->n_leaves == (1ull << (2 * d.L))) return;
+    if (EMIT && !d.full_outputs && sc->n_leaves == (1ull << (2 * d.L)) && !stale) return;
     const uint32_t ngroups = 1u << (2 * d.group_level);
     const uint32_t g = lb * kBlock + threadIdx.x;
     const bool active = g < ngroups;
@@ -638,12 +675,23 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     // consecutive lanes on consecutive entries.
     __shared__ uint32_t stage[kBlock * 16];
     if (active) {
+        // the map byte of the wave's span as the previous tree left it; the
+        // same lane overwrites it below, after this load
+        const uint64_t span0 = (uint64_t)(g - (threadIdx.x & (kWave - 1u))) << 4;
+        const int old = stale ? (int)glob(static_cast<const uint8_t*>(d.lmap))[span0] : 255;
         group_leaves<true>(d, g, code, stage + excl, big, lvl);
         glob(d.big_src)[g] = big;
         write_level_map(d, g, lvl);
+        // a stale span this tree refines is made whole before FV1 reads it
+        const int now = (int)uniform(lvl[0]);
+        if (old <= d.L - 5 && now > d.L - 5) {
+            const int cur = uniform((int)sc->cur);
+            if (d.precision == HW_FP64) fill_span<double>(d, cur, span0);
+            else fill_span<float>(d, cur, span0);
+        }
     }
-    // the map now describes this step's tree
-    if (lb == 0 && threadIdx.x == 0) glob(d.scal)->map_step = (uint32_t)(d.scal->step + 1);
+    // a standalone traversal replaces the tree the current set was made with
+    if (d.full_outputs && lb == 0 && threadIdx.x == 0) glob(d.scal)->map_step = 0u;
     __syncthreads();
     const gp<uint32_t> out = glob(d.leaves) + glob(d.tcount)[lb];
     for (uint32_t i = threadIdx.x; i < total; i += kBlock) out[i] = stage[i];
@@ -837,22 +885,6 @@ __device__ inline Cell<T> ghost_cell(const Fv1Ctx<T>& x, int dir, const Cell<T>&
         else g.qy = -g.qy;
     }
     return g;
-}
-
-template <typename T>
-__device__ inline void store_run(gp<T> p, uint32_t cnt, T v)
-{
-    if (cnt == 1) {
-        p[0] = v;
-        return;
-    }
-    if (sizeof(T) == 8) {
-        const vd2 w = {(double)v, (double)v};
-        for (uint32_t q = 0; q < cnt; q += 2) *reinterpret_cast<gp<vd2>>(p + q) = w;
-    } else {
-        const vf4 w = {(float)v, (float)v, (float)v, (float)v};
-        for (uint32_t q = 0; q < cnt; q += 4) *reinterpret_cast<gp<vf4>>(p + q) = w;
-    }
 }
 
 // 1/h for a wet depth, 0 for a dry one (velocities are then 0).
@@ -1757,6 +1789,18 @@ __global__ __launch_bounds__(kBlock) void k_fill(Launch lc)
     __builtin_amdgcn_wave_barrier();
     const int sh = 2 * (L - Lg);                      // log2 of cells per group
     const uint64_t first = (uint64_t)(g - lane) << sh;  // first cell of the wave's groups
+    // The wave's groups are one span; under one leaf at level <= L-5 only
+    // groups 0, 16, 32 and 48 are written (what the next encoding reads).
+    const uint32_t src0 = uniform(s_src[w0]);
+    if (sparse_fine(d) && src0 != kNone && level_of(src0) <= L - 5) {
+        const uint32_t q = w0 + 16u * (lane >> 4);
+        const uint64_t cell = first + 256u * (lane >> 4) + (lane & 15u);
+        if (cell != s_f0[q]) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) a[v][cell] = s_val[v][q];
+        }
+        return;
+    }
     for (uint32_t c = lane; c < (kWave << sh); c += kWave) {
         const uint32_t q = w0 + (c >> sh);
         const uint32_t sq = s_src[q];
@@ -1786,6 +1830,8 @@ __global__ __launch_bounds__(kFinalBlock) void k_finalize(const Desc* descs,
     // still reads them and writes nothing.
     const uint32_t done = sc->done;
     const double t = sc->t, dt = sc->dt;
+    const uint64_t step = sc->step;
+    const uint32_t map_step = sc->map_step;
     Acc a;
     acc_reset(a);
     const gp<const vd2> pr = reinterpret_cast<gp<const vd2>>(glob(d.partials));
@@ -1833,9 +1879,15 @@ __global__ __launch_bounds__(kFinalBlock) void k_finalize(const Desc* descs,
         sc->smax[0] = tot[1] > 1.0 ? tot[1] : 1.0;
         sc->smax[1] = tot[2] > 1.0 ? tot[2] : 1.0;
         sc->smax[2] = tot[3] > 1.0 ? tot[3] : 1.0;
-        sc->step += 1;
+        sc->step = step + 1;
         const uint64_t nl = d.uniform ? (1ull << (2 * d.L)) : sc->n_leaves;
         sc->n_leaves = nl;
+        // The traversal of this step wrote the leaf-level map (the cases in
+        // which its emit pass runs): the map describes the tree whose
+        // copy-down made the set the next step reads.
+        const bool stale = sparse_fine(d) && step > 0 && map_step == (uint32_t)step;
+        if (!d.uniform && (d.full_outputs || nl < (1ull << (2 * d.L)) || stale))
+            sc->map_step = (uint32_t)(step + 1);
         sc->leaf_updates += nl;
         sc->clips += (uint64_t)tot[5];
         sc->dry_stored += (uint64_t)tot[8];
@@ -2097,6 +2149,22 @@ hipError_t launch_fv1(int prec, const Desc* descs, int n, uint32_t grid,
 
 // Clears the FV1 write history of one problem (every entry then names no
 // step, so the next two steps store everything).
+// End of a run: every span of the current set that the last copy-down left
+// stale (covered by one leaf of the last tree at level <= L-5) is made
+// whole from its first cell.  One wave per span.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_densify(const Desc* dd)
+{
+    const Desc& d = *dd;
+    const hw_scalars* sc = d.scal;
+    if (!sparse_fine(d) || sc->step == 0 || sc->map_step != (uint32_t)sc->step) return;
+    const uint64_t span = (uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (span >= (1ull << (2 * d.L - 10))) return;
+    const uint64_t first = span << 10;
+    if ((int)glob(static_cast<const uint8_t*>(d.lmap))[first] > d.L - 5) return;
+    fill_span<T>(d, uniform((int)sc->cur), first);
+}
+
 __global__ __launch_bounds__(kBlock) void k_forget(const Desc* dd)
 {
     const gp<uint64_t> hist = glob(dd->hist);
@@ -2111,6 +2179,17 @@ hipError_t launch_forget(const Desc* dd, uint64_t nhist, hipStream_t s)
     uint64_t blocks = (nhist + kBlock - 1) / kBlock;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_forget, dim3((uint32_t)blocks), dim3(kBlock), 0, s, dd);
+    return hipGetLastError();
+}
+
+hipError_t launch_densify(int prec, const Desc* dd, int L, hipStream_t s)
+{
+    if (L < 7) return hipSuccess;
+    const uint32_t blocks = (uint32_t)(1ull << (2 * L - 12));   // four spans each
+    if (prec == HW_FP64)
+        hipLaunchKernelGGL(k_densify<double>, dim3(blocks), dim3(kBlock), 0, s, dd);
+    else
+        hipLaunchKernelGGL(k_densify<float>, dim3(blocks), dim3(kBlock), 0, s, dd);
     return hipGetLastError();
 }
 

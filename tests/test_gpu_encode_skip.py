@@ -1,22 +1,27 @@
-"""GPU: the encoder's span skip (plans with encode_skip = 1).
+"""GPU: the tree-sparse finest set of plans (encode_skip, fill_skip).
 
 Below a leaf of the previous step's tree every finest cell holds that leaf's
 value (the copy-down of the FV1 update), so a wave of the first encoding
 pass whose span of 64 * cells finest cells lies inside one leaf loads the
-span's first `cells` cells on every lane.  Two checks:
+span's first `cells` cells on every lane (encode_skip).  With fill_skip the
+copy-down then writes, in each span of 1024 cells below one leaf of level
+<= L-5, only the cells that encoding reads; the traversal completes a span
+the next tree refines, and every run call ends by completing the current
+set.  Checks:
 
-* runs with the skip on and off give the same fields, scalars and leaf
+* runs with the skips on and off give the same fields, scalars and leaf
   lists bit for bit (mixed trees, FP64 and FP32 bulk, both encoding tiles,
-  a batch);
-* the skip fires and the encoder reads nothing but the span's first cells:
-  before a step, every later cell of each span that lies inside one leaf of
-  the previous tree and inside one leaf of the tree the step will use (an
-  untouched run gives it) is overwritten with different values.  Those
-  cells are then read by nobody but the encoder (the FV1 update reads
-  finest values only for leaves on the two finest levels, and replaces
-  speculative neighbour loads below a coarser leaf by the leaf's value), so
-  with the skip on the run still equals the untouched one bit for bit, and
-  with the skip off it does not."""
+  a batch), and the same complete current set after a run call and after
+  phase profiling; the standalone encoder then agrees too;
+* the skips fire and nothing reads a cell they leave out: before a step,
+  the cells of spans below one leaf of the previous tree that the next
+  encoding does not read are overwritten with different values (with
+  encode_skip alone: only spans the next tree covers too, since the FV1
+  update reads finest values of its finest leaves).  The run still equals
+  an untouched one bit for bit, and with both skips off it does not.  In
+  the fill_skip case the poisoned spans that the next tree refines must be
+  completed by the traversal, and some are.
+"""
 import sys
 
 import numpy as np
@@ -41,11 +46,21 @@ def log(*a):
     sys.stdout.flush()
 
 
-def _make(hw, w, precision, skip, cells):
+MODES = {"both": (1, 1), "encode": (1, 0), "off": (0, 0)}
+
+
+def _make(hw, w, precision, mode, cells):
     sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision=precision)
+    es, fs = MODES[mode]
     plan = hw.Plan([sim.problem], [sim.buffers],
-                   tuning=dict(encode_skip=skip, encode_cells_per_thread=cells))
+                   tuning=dict(encode_skip=es, fill_skip=fs, encode_cells_per_thread=cells))
     return sim, plan
+
+
+def _current(sim):
+    import torch
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in sim.buffers.fine[sim.scalars()["cur"]]]
 
 
 def _same(a, b):
@@ -63,18 +78,21 @@ CASES = [("circular_l9", lambda: W.circular_dambreak_flat(9), 60),
          ("bumps_l6", lambda: W.dambreak_bumps_l6(), 40)]
 
 
+@pytest.mark.parametrize("mode", ["both", "encode"])
 @pytest.mark.parametrize("cells", [4, 16])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
 @pytest.mark.parametrize("name,make,steps", CASES, ids=[c[0] for c in CASES])
-def test_skip_on_equals_skip_off(hw, name, make, steps, precision, cells):
+def test_skip_on_equals_skip_off(hw, name, make, steps, precision, cells, mode):
     w = make()
-    log("encode skip", name, precision, "cells", cells, "steps", steps)
-    on, pon = _make(hw, w, precision, 1, cells)
-    off, poff = _make(hw, w, precision, 0, cells)
+    log("skip", mode, name, precision, "cells", cells, "steps", steps)
+    on, pon = _make(hw, w, precision, mode, cells)
+    off, poff = _make(hw, w, precision, "off", cells)
     a = hw.hwfv1_run(on.problem, on.buffers, steps, plan=pon)
     b = hw.hwfv1_run(off.problem, off.buffers, steps, plan=poff)
     assert a["steps"] == b["steps"]
     _same(on, off)
+    for x, y in zip(_current(on), _current(off)):
+        assert np.array_equal(x, y)
     log("  leaves", on.scalars()["n_leaves"], "of", 4 ** w.L)
     for x in (pon, poff):
         x.close()
@@ -89,13 +107,41 @@ def test_skip_in_a_batch(hw):
     for skip in (1, 0):
         sims = [hw.Simulation(w.params, w.h, w.qx, w.qy, w.z) for w in ws]
         plan = hw.Plan([s.problem for s in sims], [s.buffers for s in sims],
-                       tuning=dict(encode_skip=skip, encode_cells_per_thread=4))
+                       tuning=dict(encode_skip=skip, fill_skip=skip, encode_cells_per_thread=4))
         hw.hwfv1_run_batch(plan, 50)
         plan.close()
         runs.append(sims)
     for a, b in zip(*runs):
         _same(a, b)
+        for x, y in zip(_current(a), _current(b)):
+            assert np.array_equal(x, y)
     for s in runs[0] + runs[1]:
+        s.close()
+
+
+def test_profiling_and_standalone_encoder_after_a_run(hw):
+    """Phase profiling ends with a complete current set, and the standalone
+    encoder (which reads every finest cell) then gives what it gives after
+    a run without the skips."""
+    import torch
+    w = W.circular_dambreak_flat(9)
+    sims = []
+    for mode in ("both", "off"):
+        sim, plan = _make(hw, w, "fp64", mode, 4)
+        hw.hwfv1_run(sim.problem, sim.buffers, 30, plan=plan)
+        hw.hw_plan_profile(plan, 7)
+        plan.close()
+        sims.append(sim)
+    a, b = sims
+    for x, y in zip(_current(a), _current(b)):
+        assert np.array_equal(x, y)
+    for s in sims:
+        hw.mra_encode(s.problem, s.buffers)
+    torch.cuda.synchronize()
+    for x, y in zip(a.buffers.coarse, b.buffers.coarse):
+        assert torch.equal(x, y)
+    _same(a, b)
+    for s in sims:
         s.close()
 
 
@@ -115,10 +161,11 @@ def _spans(leaves, L, span_log4):
     return np.concatenate(spans) if spans else np.zeros(0, dtype=np.int64)
 
 
-def _poison(sim, spans, span_log4, cells):
+def _poison(sim, spans, span_log4, offsets):
+    """Overwrite the cells at the given offsets of each span."""
     import torch
     S = 4 ** span_log4
-    idx = (spans[:, None] * S + np.arange(cells, S)[None, :]).ravel()
+    idx = (spans[:, None] * S + offsets[None, :]).ravel()
     torch.cuda.synchronize()
     if idx.size:
         t = torch.from_numpy(idx).to(sim.buffers.fine[0][0].device)
@@ -130,29 +177,43 @@ def _poison(sim, spans, span_log4, cells):
     return int(idx.size)
 
 
+@pytest.mark.parametrize("mode", ["encode", "both"])
 @pytest.mark.parametrize("cells", [4, 16])
-def test_skip_reads_only_the_span_first_cells(hw, cells):
+def test_skipped_cells_are_read_by_nobody(hw, cells, mode):
     w = W.circular_dambreak_flat(9)
     L = w.L
-    k = 4 if cells == 4 else 5
-    ref, pref = _make(hw, w, "fp64", 1, cells)
-    on, pon = _make(hw, w, "fp64", 1, cells)
-    off, poff = _make(hw, w, "fp64", 0, cells)
-    poisoned = 0
-    for step in range(25):
+    if mode == "both":
+        # spans of 1024 cells below a leaf of level <= L-5; the encoder reads
+        # the first `cells` cells of each run of 64 * cells
+        k = 5
+        off = np.arange(1024)
+        offsets = off[(off % (64 * cells)) >= cells]
+    else:
+        k = 4 if cells == 4 else 5
+        offsets = np.arange(cells, 4 ** k)
+    ref, pref = _make(hw, w, "fp64", "off", cells)
+    on, pon = _make(hw, w, "fp64", mode, cells)
+    off_, poff = _make(hw, w, "fp64", "off", cells)
+    poisoned = refined = 0
+    for step in range(60):
         hw.hwfv1_run(ref.problem, ref.buffers, 1, plan=pref)
         if step >= 2:
-            sp = np.intersect1d(_spans(on.buffers.leaf_list(), L, k),
-                                _spans(ref.buffers.leaf_list(), L, k))
-            poisoned += _poison(on, sp, k, cells)
-            _poison(off, sp, k, cells)
-        for sim, plan in ((on, pon), (off, poff)):
+            prev = _spans(on.buffers.leaf_list(), L, k)
+            nxt = _spans(ref.buffers.leaf_list(), L, k)
+            sp = prev if mode == "both" else np.intersect1d(prev, nxt)
+            refined += int(np.setdiff1d(prev, nxt).size)
+            poisoned += _poison(on, sp, k, offsets)
+            _poison(off_, sp, k, offsets)
+        for sim, plan in ((on, pon), (off_, poff)):
             hw.hwfv1_run(sim.problem, sim.buffers, 1, plan=plan)
-    log("  poisoned cells over the run", poisoned, "cells/thread", cells)
+    log("  poisoned cells", poisoned, "spans refined by the next tree", refined,
+        "cells/thread", cells, mode)
     assert poisoned > 0
+    if mode == "both":
+        assert refined > 0
     _same(on, ref)
-    assert any(not np.array_equal(x, y) for x, y in zip(off.export(), ref.export()))
+    assert any(not np.array_equal(x, y) for x, y in zip(off_.export(), ref.export()))
     for x in (pref, pon, poff):
         x.close()
-    for s in (ref, on, off):
+    for s in (ref, on, off_):
         s.close()
