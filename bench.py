@@ -272,7 +272,7 @@ def bench_batch(hw, steps, warmup, n_members):
     return out
 
 
-def run_to_end_ms(hw, w, uniform):
+def run_to_end_ms(hw, w, uniform, tuning=None):
     """Milliseconds (HIP events) of a FP64 run from the workload's initial
     state to its t_end, on a plan that has already been captured: a first
     run counts the steps, the state is ingested again and exactly that many
@@ -280,7 +280,7 @@ def run_to_end_ms(hw, w, uniform):
     import numpy as np
     import torch
     sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision="fp64")
-    plan = hw.Plan([sim.problem], [sim.buffers], uniform=uniform)
+    plan = hw.Plan([sim.problem], [sim.buffers], tuning=tuning, uniform=uniform)
     st = hw.hwfv1_run(sim.problem, sim.buffers, 10 ** 7, plan=plan, stats=True)
     n = st["steps"]
     leaves = st["leaf_updates"] / max(n, 1)
@@ -310,15 +310,26 @@ def bench_speedup(hw, levels=(8, 9, 10, 11, 12), epss=(1e-4, 1e-3, 1e-2)):
         um, un, _, _ = run_to_end_ms(hw, W.circular_dambreak_flat(L), True)
         for eps in epss:
             ms, n, leaves, t = run_to_end_ms(hw, W.circular_dambreak_flat(L, eps), False)
-            rows.append({"L": L, "eps": eps, "steps": n, "hwfv1_ms": round(ms, 3),
-                         "uniform_fv1_ms": round(um, 3), "speedup": round(um / ms, 3),
-                         "mean_leaf_fraction": round(leaves / 4 ** L, 4)})
+            row = {"L": L, "eps": eps, "steps": n, "hwfv1_ms": round(ms, 3),
+                   "uniform_fv1_ms": round(um, 3), "speedup": round(um / ms, 3),
+                   "mean_leaf_fraction": round(leaves / 4 ** L, 4)}
+            if eps == 1e-3 and L >= 10:
+                # the same run with every finest cell read and written each step
+                dm, _, _, _ = run_to_end_ms(hw, W.circular_dambreak_flat(L, eps), False,
+                                            tuning=dict(encode_skip=0, fill_skip=0))
+                row["hwfv1_dense_ms"] = round(dm, 3)
+                row["speedup_dense"] = round(um / dm, 3)
+            rows.append(row)
             log(f"[bench] speed-up L={L} eps={eps}: {n} steps, HWFV1 {ms:.1f} ms, "
                 f"uniform {um:.1f} ms ({un} steps), x{um / ms:.2f}, "
-                f"leaves {leaves / 4 ** L:.3f}")
+                f"leaves {leaves / 4 ** L:.3f}"
+                + (f", dense HWFV1 {row['hwfv1_dense_ms']:.1f} ms" if "hwfv1_dense_ms" in row else ""))
     return {"workload": "circular_dambreak_flat (closed 40 m square, flat, frictionless, "
                         "2.5 m / 0.5 m, dam radius 2.5 m off-centre by (1.3, 0.7) m, to t = 3.5 s)",
-            "precision": "fp64", "unit": "ms to t_end (HIP events)", "rows": rows}
+            "precision": "fp64", "unit": "ms to t_end (HIP events)",
+            "note": "hwfv1_ms with the default plan (tree-sparse finest set: encode_skip, "
+                    "fill_skip); hwfv1_dense_ms with both off",
+            "rows": rows}
 
 
 def run_history_ms(hw, w, uniform, chunk):

@@ -3,7 +3,10 @@
 Chooses, for a given set of problems (one, or a batch), the encoding tile
 (4 or 16 finest cells per thread, i.e. tiles of 4^5 or 4^6 cells and 5 or 6
 levels fused per pass) and the number of persistent FV1 workgroups, by timing
-each candidate's captured step graph on the problems themselves.  The state
+each candidate's captured step graph on the problems themselves, and then
+whether the best shape runs with the tree-sparse finest set (the default) or
+reads and writes every finest cell (encode_skip = fill_skip = 0), which can
+be slightly faster when every leaf is finest.  The state
 (both finest sets and the scalars) is saved before and restored after every
 candidate (and the FV1 write history forgotten), so tuning leaves the
 simulation where it was.  Results are cached
@@ -98,6 +101,24 @@ def autotune(problems, buffers, steps=10, warmup=2, candidates=None,
     torch.cuda.synchronize()
     results.sort(key=lambda r: r[0])
     best = results[0][1]
+    if candidates is None:
+        # The tree-sparse finest set (on by default) against reading and
+        # writing every finest cell, with the best launch shape: each timed
+        # twice, alternately; it is kept unless the dense form is clearly
+        # faster on this state.
+        dense = dict(best, encode_skip=0, fill_skip=0)
+        t_on = t_off = float("inf")
+        for _ in range(2):
+            for cand in (best, dense):
+                ms = _time(problems, buffers, cand, 2 * steps, warmup)
+                _restore(problems, buffers, snap)
+                if cand is best:
+                    t_on = min(t_on, ms)
+                else:
+                    t_off = min(t_off, ms)
+        results.append((t_off, dense))
+        if t_off < 0.997 * t_on:
+            best = dense
     table = {json.dumps(c, sort_keys=True): round(ms, 5) for ms, c in results}
     if cache_path:
         cache[key] = {"best": best, "ms_per_step": table}

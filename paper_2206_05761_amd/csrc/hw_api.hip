@@ -23,7 +23,7 @@ hipError_t launch_ingest(int prec, const Desc* dd, uint32_t grid,
 hipError_t launch_encode_bed(Launch lc, uint32_t nblocks, int pass, int tl,
                              int cpt, hipStream_t s);
 hipError_t launch_encode_flow(int prec, Launch lc, uint32_t nblocks, int pass,
-                              int tl, int cpt, double* details, hipStream_t s);
+                              int tl, int cpt, bool skip, double* details, hipStream_t s);
 hipError_t launch_flag_only(int prec, Launch lc, uint32_t nblocks, hipStream_t s);
 hipError_t launch_regularise(Launch lc, uint32_t nblocks, hipStream_t s);
 hipError_t launch_traverse(Launch lc, uint32_t nblocks, hipStream_t s);
@@ -297,6 +297,7 @@ struct hw_plan {
     int tl = 5, cp = 1;
     uint32_t fv1_grid = 8;
     int write_skip = 1;
+    int encode_skip = 1;
     bool uniform = false;                     // uniform FV1 plan (FV1 and finalize only)
     std::vector<hw_problem> problems;
     std::vector<hw_buffers> buffers;
@@ -335,7 +336,8 @@ hipError_t enqueue_phase(hw_plan* pl, int phase, hipStream_t s)
             if (!pl->enc_blocks[k]) continue;
             e = hw::launch_encode_flow(pl->precision,
                                        Launch{pl->d_desc, pl->enc_prefix[k], n},
-                                       pl->enc_blocks[k], k, pl->tl, pl->cp, nullptr, s);
+                                       pl->enc_blocks[k], k, pl->tl, pl->cp,
+                                       pl->encode_skip != 0, nullptr, s);
         }
         break;
     case HW_PH_REGULARISE:
@@ -552,7 +554,7 @@ int mra_encode(const hw_problem* p, const hw_buffers* b, double* details,
     for (int k = 0; k < n_passes(p->L, tl); ++k) {
         hipError_t e = hw::launch_encode_flow(p->precision, Launch{dd, nullptr, 1},
                                               encode_blocks(p->L, k, tl), k, tl, cp,
-                                              details, stream);
+                                              false, details, stream);
         if (e != hipSuccess) return hip_fail(e, "encode launch");
     }
     return ok();
@@ -688,6 +690,7 @@ static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffe
     }
     pl->cp = tu.encode_cells_per_thread == 16 ? 2 : 1;
     pl->write_skip = tu.fv1_write_skip;
+    pl->encode_skip = tu.encode_skip;
     pl->tl = pass_levels(pl->cp);
     pl->fv1_grid = tu.fv1_grid > 0 ? (uint32_t)((tu.fv1_grid + 7) / 8 * 8)
                                    : default_fv1_grid(max_leaves);

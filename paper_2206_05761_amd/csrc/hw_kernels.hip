@@ -127,7 +127,7 @@ __device__ inline bool inflow_fine(bool flowing, double y0, double y1, double dy
     return hi - lo > 0.0;
 }
 
-template <typename T, int NV, bool FLOW, bool DET, int CP>
+template <typename T, int NV, bool FLOW, bool DET, int CP, bool SKIP = false>
 __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
                                                    int tl, double* details)
 {
@@ -310,43 +310,53 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     // the values are the same bits, so everything computed from them is
     // unchanged, and the span costs one or two cache lines per variable
     // instead of all its cells.
-    const bool span_skip = FLOW && pass == 0 && d.encode_skip && lv - cp >= 3 && step > 0 &&
+    const bool span_skip = SKIP && FLOW && pass == 0 && d.encode_skip && lv - cp >= 3 && step > 0 &&
                            map_step == (uint32_t)step && n_leaves < (1ull << (2 * L));
     double p[NV];
     if ((uint32_t)tid < M) {
         const uint64_t tile_in = (uint64_t)b << (2 * lv);
-        uint64_t own = tile_in + (uint64_t)cells * tid;
+        // wave-uniform: the span's first cell, and whether the span is covered
+        uint64_t wf = 0;
+        bool covered = false;
         if (span_skip) {
-            const uint64_t wf = tile_in + (uint64_t)cells * uniform((uint32_t)(tid & ~(kWave - 1)));
+            wf = tile_in + (uint64_t)cells * uniform((uint32_t)(tid & ~(kWave - 1)));
             const int span_level = L - (cells == 4 ? 4 : 5);
-            if ((int)glob(static_cast<const uint8_t*>(d.lmap))[wf] <= span_level) own = wf;
+            covered = uniform((int)glob(static_cast<const uint8_t*>(d.lmap))[wf]) <= span_level;
         }
-        // All child loads are issued before any store of this thread.
+        // All child loads are issued before any store of this thread.  The
+        // two load forms sit in separate wave-uniform branches so that the
+        // usual one keeps its base-plus-lane-offset addressing.
         if (CP == 1 || cp == 1) {
-            const uint64_t base = own;
             double ch[NV][4];
+            auto load_children = [&](uint64_t base) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                if (FLOW && pass == 0) load4(src[v] + base, ch[v]);
-                else
+                for (int v = 0; v < NV; ++v) {
+                    if (FLOW && pass == 0) load4(src[v] + base, ch[v]);
+                    else
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) ch[v][q] = (double)src[v][base + q];
-            }
+                        for (int q = 0; q < 4; ++q) ch[v][q] = (double)src[v][base + q];
+                }
+            };
+            if (covered) load_children(wf);
+            else load_children(tile_in + 4ull * tid);
             if (blocks) block_test(ch[0]);
             emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + tid, ch, p, zr[0]);
         } else {
-            const uint64_t base = own;
             double ch[4][NV][4];
+            auto load_children = [&](uint64_t base) {
 #pragma unroll
-            for (int qq = 0; qq < 4; ++qq)
+                for (int qq = 0; qq < 4; ++qq)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    if (FLOW && pass == 0) load4(src[v] + base + 4 * qq, ch[qq][v]);
-                    else
+                    for (int v = 0; v < NV; ++v) {
+                        if (FLOW && pass == 0) load4(src[v] + base + 4 * qq, ch[qq][v]);
+                        else
 #pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            ch[qq][v][q] = (double)src[v][base + 4 * qq + q];
-                }
+                            for (int q = 0; q < 4; ++q)
+                                ch[qq][v][q] = (double)src[v][base + 4 * qq + q];
+                    }
+            };
+            if (covered) load_children(wf);
+            else load_children(tile_in + 16ull * tid);
             if (blocks) {
                 double hs[16];
 #pragma unroll
@@ -637,16 +647,19 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     uint32_t lb;
     const int s = scen_of(lc, blockIdx.x, lb);
     const Desc& d = lc.descs[s];
-    const hw_scalars* sc = d.scal;
-    if (sc->done) return;
+    // every scalar the exit tests read, requested together
+    const gp<const hw_scalars> sc = glob(static_cast<const hw_scalars*>(d.scal));
+    const uint32_t done = sc->done;
+    const uint64_t n_leaves = sc->n_leaves, step = sc->step;
+    const uint32_t map_step = sc->map_step, cur = sc->cur;
+    if (done) return;
     // Spans of the current set may be stale when the previous step's tree
     // covered them (the map still describes that tree: it was written in
     // the step that made the set).
-    const bool stale = EMIT && sparse_fine(d) && sc->step > 0 &&
-                       sc->map_step == (uint32_t)sc->step;
+    const bool stale = EMIT && sparse_fine(d) && step > 0 && map_step == (uint32_t)step;
     // In the time loop a step whose leaves are all finest needs no list,
     // map or fill table: the FV1 kernels take that case from n_leaves.
-    if (EMIT && !d.full_outputs && sc->n_leaves == (1ull << (2 * d.L)) && !stale) return;
+    if (EMIT && !d.full_outputs && n_leaves == (1ull << (2 * d.L)) && !stale) return;
     const uint32_t ngroups = 1u << (2 * d.group_level);
     const uint32_t g = lb * kBlock + threadIdx.x;
     const bool active = g < ngroups;
@@ -685,9 +698,8 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
         // a stale span this tree refines is made whole before FV1 reads it
         const int now = (int)uniform(lvl[0]);
         if (old <= d.L - 5 && now > d.L - 5) {
-            const int cur = uniform((int)sc->cur);
-            if (d.precision == HW_FP64) fill_span<double>(d, cur, span0);
-            else fill_span<float>(d, cur, span0);
+            if (d.precision == HW_FP64) fill_span<double>(d, (int)cur, span0);
+            else fill_span<float>(d, (int)cur, span0);
         }
     }
     // a standalone traversal replaces the tree the current set was made with
@@ -2053,25 +2065,34 @@ hipError_t launch_encode_bed(Launch lc, uint32_t nblocks, int pass, int tl,
 
 template <typename T, bool DET>
 static void encode_flow_t(Launch lc, uint32_t nblocks, int pass, int tl, int cpt,
-                          double* details, hipStream_t s)
+                          bool skip, double* details, hipStream_t s)
 {
-    if (cpt == 2)
+    // the span skip exists in the first pass of plans that allow it only
+    if (skip && !DET && pass == 0) {
+        if (cpt == 2)
+            hipLaunchKernelGGL((k_encode<T, 3, true, false, 2, true>), dim3(nblocks), dim3(kBlock),
+                               0, s, lc, pass, tl, details);
+        else
+            hipLaunchKernelGGL((k_encode<T, 3, true, false, 1, true>), dim3(nblocks), dim3(kBlock),
+                               0, s, lc, pass, tl, details);
+    } else if (cpt == 2) {
         hipLaunchKernelGGL((k_encode<T, 3, true, DET, 2>), dim3(nblocks), dim3(kBlock), 0, s,
                            lc, pass, tl, details);
-    else
+    } else {
         hipLaunchKernelGGL((k_encode<T, 3, true, DET, 1>), dim3(nblocks), dim3(kBlock), 0, s,
                            lc, pass, tl, details);
+    }
 }
 
 hipError_t launch_encode_flow(int prec, Launch lc, uint32_t nblocks, int pass,
-                              int tl, int cpt, double* details, hipStream_t s)
+                              int tl, int cpt, bool skip, double* details, hipStream_t s)
 {
     if (prec == HW_FP64) {
-        if (details) encode_flow_t<double, true>(lc, nblocks, pass, tl, cpt, details, s);
-        else encode_flow_t<double, false>(lc, nblocks, pass, tl, cpt, details, s);
+        if (details) encode_flow_t<double, true>(lc, nblocks, pass, tl, cpt, skip, details, s);
+        else encode_flow_t<double, false>(lc, nblocks, pass, tl, cpt, skip, details, s);
     } else {
-        if (details) encode_flow_t<float, true>(lc, nblocks, pass, tl, cpt, details, s);
-        else encode_flow_t<float, false>(lc, nblocks, pass, tl, cpt, details, s);
+        if (details) encode_flow_t<float, true>(lc, nblocks, pass, tl, cpt, skip, details, s);
+        else encode_flow_t<float, false>(lc, nblocks, pass, tl, cpt, skip, details, s);
     }
     return hipGetLastError();
 }

@@ -383,7 +383,11 @@ def test_autotune_restores_state_and_picks_a_candidate(hw):
     best, table = autotune([sim.problem], [sim.buffers], steps=3, warmup=1,
                            cache_path=None)
     after = sim.export() + (sim.scalars()["t"], sim.scalars()["step"])
-    assert best in CANDIDATES and len(table) == len(CANDIDATES)
+    # a launch shape of the list, with the tree-sparse finest set on (the
+    # default) or both of its skips off; one more timing for that choice
+    shape = {k: v for k, v in best.items() if k not in ("encode_skip", "fill_skip")}
+    assert shape in CANDIDATES and len(table) == len(CANDIDATES) + 1
+    assert best == shape or (best["encode_skip"], best["fill_skip"]) == (0, 0)
     for x, y in zip(before[:3], after[:3]):
         assert np.array_equal(x, y)
     assert before[3:] == after[3:]
