@@ -421,10 +421,11 @@ def main():
                     help="skip the uniform-FV1 comparisons")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the no-write-skip and fully wet FP64 runs")
-    ap.add_argument("--tuning", default=None, metavar="CPT,GRID",
+    ap.add_argument("--tuning", default=None, metavar="CPT,GRID[,SPARSE]",
                     help="fixed launch shape for the single-problem runs "
-                         "(encode cells per thread, FV1 workgroups) instead of "
-                         "the autotuner, e.g. 4,2048")
+                         "(encode cells per thread, FV1 workgroups, and optionally "
+                         "1/0 for the tree-sparse finest set on/off) instead of "
+                         "the autotuner, e.g. 4,2048 or 4,1024,0")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB three "
                          "times (reference kernel for HBM counter scaling)")
@@ -446,8 +447,10 @@ def main():
     hw.lib()
     tuning = None
     if args.tuning:
-        cpt, grid = (int(v) for v in args.tuning.split(","))
-        tuning = dict(encode_cells_per_thread=cpt, fv1_grid=grid)
+        vals = [int(v) for v in args.tuning.split(",")]
+        tuning = dict(encode_cells_per_thread=vals[0], fv1_grid=vals[1])
+        if len(vals) > 2:
+            tuning.update(encode_skip=vals[2], fill_skip=vals[2])
     w = W.hydrograph_l12()
     L = w.L
     r64 = time_single(hw, w, "fp64", args.steps, args.warmup, args.prof_steps, tuning)
