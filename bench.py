@@ -429,6 +429,11 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB three "
                          "times (reference kernel for HBM counter scaling)")
+    ap.add_argument("--circular", type=int, default=None, metavar="L",
+                    help="profiling mode: only run the circular dam break at level L "
+                         "(eps 1e-3) from its initial state to t_end, with the "
+                         "tree-sparse finest set on or off (--sparse), and print its time")
+    ap.add_argument("--sparse", type=int, default=1, choices=(0, 1))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -445,6 +450,16 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     hw.lib()
+    if args.circular is not None:
+        w = W.circular_dambreak_flat(args.circular, 1e-3)
+        ms, n, leaves, t = run_to_end_ms(hw, w, False, tuning=dict(
+            encode_skip=args.sparse, fill_skip=args.sparse))
+        print(json.dumps({"workload": w.name, "L": args.circular, "eps": 1e-3,
+                          "tree_sparse": bool(args.sparse), "steps": n, "t": t,
+                          "ms_to_t_end": round(ms, 3), "ms_per_step": round(ms / n, 5),
+                          "mean_leaf_fraction": round(leaves / 4 ** args.circular, 4)}),
+              flush=True)
+        return
     tuning = None
     if args.tuning:
         vals = [int(v) for v in args.tuning.split(",")]
