@@ -139,10 +139,12 @@ typedef struct hw_scalars {
     uint32_t cur;        /* finest set (0 or 1) holding the current state  */
     uint32_t done;       /* 1 once t >= t_end                              */
     uint32_t nonfinite;  /* 1 if a non-finite value was produced           */
-    uint32_t map_step;   /* step + 1 (low 32 bits) of the step whose
-                            traversal last wrote the leaf-level map, 0 after
-                            hw_ingest; equal to step when the map describes
-                            the tree whose copy-down made the current set  */
+    uint32_t map_step;   /* equal to step (low 32 bits) when the leaf-level
+                            map describes the tree whose copy-down made the
+                            current set: written by the FV1 finalisation of
+                            a step whose traversal wrote the map; 0 after
+                            hw_ingest, hw_forget and a standalone traversal
+                            (the next encoding then reads every cell)      */
 } hw_scalars;
 
 /*
