@@ -75,7 +75,28 @@ CASES = [("circular_l9", lambda: W.circular_dambreak_flat(9), 60),
          ("pseudo2d_l9", lambda: W.pseudo2d_dambreak(9), 60),
          ("channel_l8", lambda: W.pseudo2d_channel(8), 60),
          ("hydrograph_l8", lambda: W.hydrograph_l12(L=8), 40),
-         ("bumps_l6", lambda: W.dambreak_bumps_l6(), 40)]
+         ("bumps_l6", lambda: W.dambreak_bumps_l6(), 40),
+         # flat bed, dry outside the dam: about 9 in 10 cells below dry coarse
+         # leaves of level <= L-5 (dry shortcut inside covered spans) ...
+         ("circular_dry_l9", lambda: _circular_dry(0.0), 60),
+         # ... and the same with rain falling on it (no dry shortcut)
+         ("circular_dry_rain_l9", lambda: _circular_dry(1.4e-5), 60),
+         # rough beds: every leaf finest, the skips never fire (controls)
+         ("sheetflow_l8", lambda: W.sheetflow_l13(L=8), 30),
+         ("dry_patches_l9_inlet", lambda: _patches(), 30)]
+
+
+def _circular_dry(rain):
+    w = W.circular_dambreak_flat(9)
+    w.h = np.where(w.h > 1.0, w.h, 0.0)
+    w.params = dict(w.params, rain_rate=rain)
+    return w
+
+
+def _patches():
+    w = W.dry_patches(9, 5, inlet=True, rain=0.0)
+    w.params = dict(w.params, t_end=float("inf"))
+    return w
 
 
 @pytest.mark.parametrize("mode", ["both", "encode"])
@@ -177,10 +198,11 @@ def _poison(sim, spans, span_log4, offsets):
     return int(idx.size)
 
 
+@pytest.mark.parametrize("dry", [False, True])
 @pytest.mark.parametrize("mode", ["encode", "both"])
 @pytest.mark.parametrize("cells", [4, 16])
-def test_skipped_cells_are_read_by_nobody(hw, cells, mode):
-    w = W.circular_dambreak_flat(9)
+def test_skipped_cells_are_read_by_nobody(hw, cells, mode, dry):
+    w = _circular_dry(0.0) if dry else W.circular_dambreak_flat(9)
     L = w.L
     if mode == "both":
         # spans of 1024 cells below a leaf of level <= L-5; the encoder reads
