@@ -434,6 +434,9 @@ def main():
                          "(eps 1e-3) from its initial state to t_end, with the "
                          "tree-sparse finest set on or off (--sparse), and print its time")
     ap.add_argument("--sparse", type=int, default=1, choices=(0, 1))
+    ap.add_argument("--circular-steps", type=int, default=0, metavar="K",
+                    help="with --circular: run only the first K steps, once "
+                         "(for counter collection), instead of to t_end")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -452,8 +455,22 @@ def main():
     hw.lib()
     if args.circular is not None:
         w = W.circular_dambreak_flat(args.circular, 1e-3)
-        ms, n, leaves, t = run_to_end_ms(hw, w, False, tuning=dict(
-            encode_skip=args.sparse, fill_skip=args.sparse))
+        tu = dict(encode_skip=args.sparse, fill_skip=args.sparse)
+        if args.circular_steps > 0:
+            sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision="fp64")
+            plan = hw.Plan([sim.problem], [sim.buffers], tuning=tu)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            st = hw.hwfv1_run(sim.problem, sim.buffers, args.circular_steps, plan=plan)
+            e1.record()
+            torch.cuda.synchronize()
+            ms, n, t = e0.elapsed_time(e1), st["steps"], st["t"]
+            leaves = st["leaf_updates"] / max(n, 1)
+            plan.close()
+            sim.close()
+        else:
+            ms, n, leaves, t = run_to_end_ms(hw, w, False, tuning=tu)
         print(json.dumps({"workload": w.name, "L": args.circular, "eps": 1e-3,
                           "tree_sparse": bool(args.sparse), "steps": n, "t": t,
                           "ms_to_t_end": round(ms, 3), "ms_per_step": round(ms / n, 5),
