@@ -290,6 +290,51 @@ def pseudo2d_channel(L: int = 8, eps: float = 1e-3, t_end: float = 40.0) -> Work
     return w
 
 
+HUMP_ETA = {"smooth": 0.875, "steeper": 1.78, "rectangular": 1.95}
+
+
+def humps_lake_at_rest(profile: str, L: int = 8, eps: float = 1e-3,
+                       t_end: float = 100.0) -> Workload:
+    """Still water over three humps in a closed 70 m x 30 m basin (the
+    well-balancedness case of Section 3.1, whose hump shapes are only
+    drawn): free surface eta of Table 3, zero discharges.  Humps at (30, 6),
+    (30, 24) and (47.5, 15) m, chosen so that the water is dry around the
+    highest one, critical (h = 0) at the peak of the one whose peak equals
+    eta, and wet above the lowest:
+      smooth       cones of peak 0.875, 0.875, 3 m and radius 8, 8, 10 m;
+      steeper      cones of peak 1.0, 1.78, 3 m and radius 2.5, 3, 5 m;
+      rectangular  square blocks of height 1.0, 1.95, 3 m and side 6, 6, 8 m.
+    The basin is rows 0..ny-1 of the 2^L-cell-wide square grid (cell size
+    70 / 2^L, ny = 30 m / cell rounded), the rows above are dry ground
+    1000 m above the water (a closed edge, like the walls)."""
+    eta = HUMP_ETA[profile]
+    length = 70.0
+    n = 1 << L
+    dx = length / n
+    ny = int(round(30.0 / dx))
+    p = base_params(L, length, eps, bc=("wall",) * 4, t_end=t_end,
+                    dt_max=0.5 * dx / math.sqrt(G * 1e-3))
+    x, y = cell_centres(L, length)
+    centres = [(30.0, 6.0), (30.0, 24.0), (47.5, 15.0)]
+    z = np.zeros((n, n))
+    if profile == "rectangular":
+        for (cx, cy), top, side in zip(centres, (1.0, 1.95, 3.0), (6.0, 6.0, 8.0)):
+            inside = (np.abs(x - cx) <= side / 2) & (np.abs(y - cy) <= side / 2)
+            z = np.where(inside, np.maximum(z, top), z)
+    else:
+        peaks, radii = {"smooth": ((0.875, 0.875, 3.0), (8.0, 8.0, 10.0)),
+                        "steeper": ((1.0, 1.78, 3.0), (2.5, 3.0, 5.0))}[profile]
+        for (cx, cy), top, rad in zip(centres, peaks, radii):
+            r = np.hypot(x - cx, y - cy)
+            z = np.maximum(z, top * np.maximum(0.0, 1.0 - r / rad))
+    h = np.maximum(0.0, eta - z)
+    z[ny:, :] = 1000.0
+    h[ny:, :] = 0.0
+    zero = np.zeros_like(h)
+    return Workload(f"humps_{profile}_l{L}", p, h, zero, zero.copy(), z,
+                    n_steps=3000, meta=dict(eta=eta, basin_rows=ny, profile=profile))
+
+
 def dry_patches(L: int, seed: int, n_rect: int = 4, n_single: int = 12,
                 inlet: bool = False, rain: float = 0.0) -> Workload:
     """Mostly dry domain over a rough bed (uniform noise of 1 m on every
