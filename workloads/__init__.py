@@ -335,6 +335,23 @@ def humps_lake_at_rest(profile: str, L: int = 8, eps: float = 1e-3,
                     n_steps=3000, meta=dict(eta=eta, basin_rows=ny, profile=profile))
 
 
+def humps_dambreak(L: int = 8, eps: float = 1e-3, t_end: float = 12.0) -> Workload:
+    """The frictional dam break of Section 3.1 over the smooth humps of
+    humps_lake_at_rest: water surface 1.875 m behind a dam at x = 16 m
+    (depth 1.875 m - z where positive), dry beyond it, zero discharges,
+    Manning n = 0.018, closed 70 m x 30 m basin."""
+    w = humps_lake_at_rest("smooth", L, eps, t_end)
+    rows = w.meta["basin_rows"]
+    x, _ = cell_centres(L, 70.0)
+    h = np.where(x < 16.0, np.maximum(0.0, 1.875 - w.z), 0.0)
+    h[rows:, :] = 0.0
+    w.h = h
+    w.params = dict(w.params, manning_n=0.018)
+    w.name = f"humps_dambreak_l{L}"
+    w.meta = dict(w.meta, x_dam=16.0, surface=1.875)
+    return w
+
+
 def dry_patches(L: int, seed: int, n_rect: int = 4, n_single: int = 12,
                 inlet: bool = False, rain: float = 0.0) -> Workload:
     """Mostly dry domain over a rough bed (uniform noise of 1 m on every
