@@ -361,6 +361,44 @@ def run_history_ms(hw, w, uniform, chunk):
     return hist, steps
 
 
+def bench_verification(hw):
+    """Section 3.1's cases on the hump shapes of workloads.humps_lake_at_rest
+    (FP64, L = 8, eps = 1e-3): the largest discharge over 100 s of still
+    water per profile (well-balancedness), and the frictional dam break's
+    mean absolute depth difference from uniform FV1 over the basin."""
+    import numpy as np
+    import workloads as W
+    out = {"lake_at_rest_max_discharge": {}, "humps_dambreak_l1_vs_uniform_m": {}}
+    for prof in ("smooth", "steeper", "rectangular"):
+        w = W.humps_lake_at_rest(prof)
+        sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z)
+        worst = 0.0
+        while sim.scalars()["t"] < w.params["t_end"]:
+            sim.run(500, stats=False)
+            _, qx, qy = sim.export()
+            worst = max(worst, float(np.abs(qx).max()), float(np.abs(qy).max()))
+        out["lake_at_rest_max_discharge"][prof] = worst
+        sim.close()
+    for t_end in (6.0, 12.0):
+        w = W.humps_dambreak(t_end=t_end)
+        rows = w.meta["basin_rows"]
+        hs = []
+        for uniform in (False, True):
+            sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z)
+            plan = hw.Plan([sim.problem], [sim.buffers], uniform=uniform)
+            hw.hwfv1_run(sim.problem, sim.buffers, 100_000, plan=plan, stats=False)
+            plan.close()
+            hs.append(sim.export()[0][:rows])
+            sim.close()
+        out["humps_dambreak_l1_vs_uniform_m"][f"{t_end:g} s"] = float(np.abs(hs[0] - hs[1]).mean())
+    out["note"] = ("hump shapes chosen to meet Table 3's wetting conditions (the paper only "
+                   "draws them); the paper's own L1 differences (4.6e-4 m at 6 s, 9.2e-4 m "
+                   "at 12 s) are context, not a target")
+    log(f"[bench] verification: {out['lake_at_rest_max_discharge']}, "
+        f"{out['humps_dambreak_l1_vs_uniform_m']}")
+    return out
+
+
 def bench_pseudo2d(hw, levels=(8, 9, 10, 11), epss=(1e-4, 1e-3, 1e-2), window=2.5, t_end=40.0):
     """Speed-up of HWFV1 over uniform FV1 through the 40 s pseudo-2D dam
     break, per window of simulated time (the paper's Fig. 14)."""
@@ -564,6 +602,7 @@ def main():
         del ru
         line["speedup_series"] = bench_speedup(hw)
         line["speedup_pseudo2d"] = bench_pseudo2d(hw)
+        line["verification"] = bench_verification(hw)
     if not args.no_fp32:
         r32 = time_single(hw, w, "fp32_bulk", args.steps, args.warmup, args.prof_steps,
                           tuning)
