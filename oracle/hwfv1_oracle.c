@@ -42,7 +42,8 @@
  *
  * Parity unpinned: the change of total mass where leaf levels jump at
  * eps > 0 has no closed form to test against (its tests bound it loosely);
- * every other step is pinned by the tests named in the design notes.
+ * every other step is pinned by tests/test_oracle_mra.py,
+ * tests/test_oracle_fv1.py and tests/test_humps.py.
  */
 #include "hwfv1_oracle.h"
 
