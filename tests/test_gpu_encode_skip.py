@@ -239,3 +239,22 @@ def test_skipped_cells_are_read_by_nobody(hw, cells, mode, dry):
         x.close()
     for s in (ref, on, off_):
         s.close()
+
+
+def test_skips_at_full_size_l12(hw):
+    """The circular dam break of the speed-up series at L = 12 (16.8 M
+    finest cells, most of them below coarse leaves), in the plan shape the
+    benchmark times: 400 steps with the skips on and off, bit for bit."""
+    w = W.circular_dambreak_flat(12)
+    on, pon = _make(hw, w, "fp64", "both", 4)
+    off, poff = _make(hw, w, "fp64", "off", 4)
+    a = hw.hwfv1_run(on.problem, on.buffers, 400, plan=pon)
+    b = hw.hwfv1_run(off.problem, off.buffers, 400, plan=poff)
+    assert a["steps"] == b["steps"] == 400
+    log("  L=12:", on.scalars()["n_leaves"], "leaves of", 4 ** 12)
+    assert 0 < on.scalars()["n_leaves"] < 4 ** 12 // 4
+    _same(on, off)
+    for x in (pon, poff):
+        x.close()
+    on.close()
+    off.close()
