@@ -66,3 +66,81 @@ def tie_band_cells(L, eps, smax, details, rel=1e-12):
         dn = np.max(np.abs(d), axis=0) / s
         band |= np.abs(dn - thr) <= rel * np.maximum(thr, 1e-300)
     return np.nonzero(band)[0]
+
+
+def part1by1(x):
+    x = np.asarray(x, dtype=np.uint64) & np.uint64(0xFFFFFFFF)
+    for s, m in ((16, 0x0000FFFF0000FFFF), (8, 0x00FF00FF00FF00FF),
+                 (4, 0x0F0F0F0F0F0F0F0F), (2, 0x3333333333333333),
+                 (1, 0x5555555555555555)):
+        x = (x | (x << np.uint64(s))) & np.uint64(m)
+    return x
+
+
+def oracle_tie_band(o, rel=1e-12):
+    """Tie band of the oracle's last encoding: coarse cells whose normalised
+    detail of h, qx, qy or the bed lies within rel of 2^(n-L) eps, with the
+    s_max values that encoding used."""
+    sc = o.scalars()
+    names = ("h", "qx", "qy", "z")
+    smax = [sc["smax_" + v] for v in names]
+    return tie_band_cells(o.L, float(o.params["eps"]), smax,
+                          [o.details(v) for v in names], rel)
+
+
+def band_region(L, ties):
+    """Finest cells (Morton order) whose leaf can change when the flags of
+    the tie cells flip: the descendants of each tie cell and of its face
+    neighbours on its level (regularisation spreads a flag to those)."""
+    mark = np.zeros((1 << (2 * L)) + 1, dtype=np.int64)
+    ties = np.asarray(ties, dtype=np.int64)
+    if ties.size == 0:
+        return np.zeros(1 << (2 * L), dtype=bool)
+    n = level_of(ties)
+    m = (ties - ((4 ** n) - 1) // 3).astype(np.uint64)
+    i = compact1by1(m).astype(np.int64)
+    j = compact1by1(m >> np.uint64(1)).astype(np.int64)
+    side = np.int64(1) << n
+    for di, dj in ((0, 0), (-1, 0), (1, 0), (0, -1), (0, 1)):
+        ii, jj = i + di, j + dj
+        ok = (ii >= 0) & (ii < side) & (jj >= 0) & (jj < side)
+        code = (part1by1(ii[ok]) | (part1by1(jj[ok]) << np.uint64(1))).astype(np.int64)
+        sh = 2 * (L - n[ok])
+        np.add.at(mark, code << sh, 1)
+        np.add.at(mark, (code + 1) << sh, -1)
+    return np.cumsum(mark[:-1]) > 0
+
+
+def leaf_of_finest(L, leaves):
+    """For every finest cell (Morton order) the leaf that contains it."""
+    leaves = np.asarray(leaves, dtype=np.int64)
+    reps = np.int64(4) ** (L - level_of(leaves))
+    out = np.repeat(leaves, reps)
+    assert out.size == 1 << (2 * L), "leaves do not tile the domain"
+    return out
+
+
+def compare_leaf_lists(L, got, want, ties, log=print):
+    """Leaf lists must be identical outside the tie band: cells whose
+    normalised detail sits within 1e-12 of the threshold are listed, and
+    only the finest cells they can affect may carry different leaves.
+    Returns the number of tie cells."""
+    got = np.asarray(got)
+    want = np.asarray(want)
+    ties = np.asarray(ties)
+    if ties.size:
+        log(f"  tie band: {ties.size} cells within 1e-12 of the threshold: "
+            f"{ties[:20].tolist()}{' ...' if ties.size > 20 else ''}")
+    else:
+        log("  tie band: none")
+    if np.array_equal(got, want):
+        return int(ties.size)
+    assert ties.size, "leaf lists differ and no cell lies in the tie band"
+    region = band_region(L, ties)
+    a, b = leaf_of_finest(L, got), leaf_of_finest(L, want)
+    outside = (a != b) & ~region
+    assert not outside.any(), (
+        f"leaf lists differ outside the tie band at {int(outside.sum())} finest cells")
+    log(f"  leaf lists differ only inside the tie band "
+        f"({int((a != b).sum())} finest cells)")
+    return int(ties.size)

@@ -155,6 +155,85 @@ def test_linear_ramp_leaf_level_closed_form():
         assert np.array_equal(leaves, np.arange(start, start + 4 ** leaf_level))
 
 
+def _uniform_leaf_level(L, ratio):
+    """Leaf level of a field whose level-n normalised detail is
+    a / (2^(n+2) s_max) against the threshold 2^(n-L) eps: every level n
+    with 4^n <= ratio = a 2^L / (4 s_max eps) is significant."""
+    nstar = int(np.floor(np.log(ratio) / np.log(4.0)))
+    return min(nstar, L - 1) + 1
+
+
+def _assert_uniform_leaves(leaves, level):
+    start = (4 ** level - 1) // 3
+    assert np.array_equal(leaves, np.arange(start, start + 4 ** level)), (
+        f"expected the uniform grid of level {level}, got {len(leaves)} leaves")
+
+
+def test_smax_of_the_bed_is_its_largest_finest_magnitude():
+    """Section 2.1.2 normalises by the largest coefficient of the finest
+    level.  A falling bed z = -(a x + c) with a = 3, c = 2 has
+    max |z^(L)| = a (1 - 2^-(L+1)) + c (the last cell centre), well above
+    the guard of 1; eps is chosen so that the closed-form leaf level with
+    that s_max differs from the one obtained with the guard value (s_max
+    = 1, as a dropped abs would give for this negative bed) and with the
+    root's magnitude (a coarse-level normaliser)."""
+    L, a, c = 7, 3.0, 2.0
+    smax = a * (1.0 - 2.0 ** -(L + 1)) + c
+    eps = a * 2 ** L / (4.0 * smax * (3.2 * 4 ** 3))   # ratio 204.8: level 4
+    p = W.base_params(L, 1.0, eps)
+    x, _ = W.cell_centres(L, 1.0)
+    z = -(a * x + c)
+    one = np.ones_like(z)
+    zero = np.zeros_like(z)
+    o = O.Oracle(p, one, zero, zero, z)
+    assert o.scalars()["smax_z"] == smax
+    o.phase_encode()
+    o.phase_regularise()
+    o.phase_traverse()
+    ratio = a * 2 ** L / (4.0 * smax * eps)
+    level = _uniform_leaf_level(L, ratio)
+    assert level == 4
+    # the misreadings give another level on this field
+    assert _uniform_leaf_level(L, a * 2 ** L / (4.0 * 1.0 * eps)) != level
+    assert _uniform_leaf_level(L, a * 2 ** L / (4.0 * (a * 0.5 + c) * eps)) != level
+    _assert_uniform_leaves(o.leaves(), level)
+
+
+def test_smax_of_the_depth_is_taken_again_every_step():
+    """s_max of a flow variable is the largest finest magnitude at the start
+    of each step.  A depth ramp h = 1 + a x (a = 3) on a flat closed basin
+    with tiny gravity (so fluxes change it by less than 1e-5) and heavy
+    rain: the first step refines to the closed-form level for
+    s_max = 1 + a (1 - 2^-(L+1)); the rain then adds R dt = 10 m to every
+    cell (details unchanged), s_max grows to the largest level-4 average
+    plus 10 and the second step's tree is one level coarser.  An s_max
+    kept from the first step, or the guard value, gives other levels."""
+    L, a = 7, 3.0
+    smax1 = 1.0 + a * (1.0 - 2.0 ** -(L + 1))
+    eps = a * 2 ** L / (4.0 * smax1 * (3.0 * 4 ** 3))   # ratio 192: level 4
+    p = W.base_params(L, 1.0, eps, g=1e-12, dt_max=1.0, rain_rate=10.0)
+    x, _ = W.cell_centres(L, 1.0)
+    h = 1.0 + a * x
+    zero = np.zeros_like(h)
+    o = O.Oracle(p, h, zero, zero.copy(), zero.copy())
+    assert o.scalars()["dt"] == 1.0
+    assert o.step()
+    level1 = _uniform_leaf_level(L, a * 2 ** L / (4.0 * smax1 * eps))
+    assert level1 == 4
+    _assert_uniform_leaves(o.leaves(), level1)
+    assert o.scalars()["smax_h"] == smax1
+    # after the step: piecewise constant on level 4, plus the rain
+    smax2 = 1.0 + a * (1.0 - 2.0 ** -5) + 10.0
+    assert o.step()
+    assert o.scalars()["smax_h"] == pytest.approx(smax2, rel=1e-6)
+    level2 = _uniform_leaf_level(L, a * 2 ** L / (4.0 * smax2 * eps))
+    assert level2 == 3
+    _assert_uniform_leaves(o.leaves(), level2)
+    # the normaliser of the first step, or the guard, would keep level 4 or more
+    assert _uniform_leaf_level(L, a * 2 ** L / (4.0 * smax1 * eps)) != level2
+    assert _uniform_leaf_level(L, a * 2 ** L / (4.0 * 1.0 * eps)) != level2
+
+
 def test_eps_zero_gives_all_finest_leaves_and_constant_gives_root():
     L = 4
     w = W.lake_at_rest(L, 0.8, 3, eps=0.0)
