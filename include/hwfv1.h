@@ -295,6 +295,32 @@ int mra_traverse_leaves(const hw_problem* p, const hw_buffers* b,
                         hipStream_t stream);
 
 /*
+ * Traversal that allocates nothing and takes no workspace: for callers that
+ * cannot allocate device memory or pass a workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * result as mra_traverse_leaves: b->leaves and hw_scalars.n_leaves (and
+ * map_step = 0).  Reads b->sig and b->scal, writes b->leaves and b->scal;
+ * b->work is ignored and may be NULL, as may every other buffer.
+ * The traversal's own scratch (descriptor, per-workgroup leaf counts, walk
+ * codes, fill table, leaf-level map) lives in one device array per GPU of
+ * hw_noalloc_scratch_bytes() bytes (levels up to 11), which the library
+ * holds until the process ends; its address is looked up on the first call
+ * on each device.  Every call on a GPU shares that array and every entry a
+ * call reads is written by the same call first, so nothing needs clearing;
+ * calls that overlap on one GPU (concurrent streams or threads) race.  The
+ * fill table and leaf-level map it builds stay in that array, so fv1_step
+ * (which reads them from b->work) must follow mra_traverse_leaves, not this
+ * variant.  Errors: HW_ECAPACITY for L > 11 (nothing launched), HW_EINVAL
+ * for a bad problem or a NULL / misaligned sig, leaves or scal, HW_EHIP on
+ * a failed symbol lookup or launch.
+ */
+int mra_traverse_leaves_noalloc(const hw_problem* p, const hw_buffers* b,
+                                hipStream_t stream);
+
+/* Bytes of the per-GPU scratch array used by mra_traverse_leaves_noalloc. */
+size_t hw_noalloc_scratch_bytes(void);
+
+/*
  * FV1 update on the leaves (Sections 2.1.1, 2.1.3, 2.2.3): for every leaf
  * (level m, cell c) the neighbour in each direction is the level-m cell on
  * that side, or the coarser leaf that contains it, or a boundary ghost;

@@ -108,6 +108,9 @@ def lib():
         L.mra_encode.argtypes = [P(HwProblem), P(HwBuffers), vp, vp]
         L.mra_flag.argtypes = [P(HwProblem), P(HwBuffers), vp]
         L.mra_traverse_leaves.argtypes = [P(HwProblem), P(HwBuffers), vp]
+        L.mra_traverse_leaves_noalloc.argtypes = [P(HwProblem), P(HwBuffers), vp]
+        L.hw_noalloc_scratch_bytes.argtypes = []
+        L.hw_noalloc_scratch_bytes.restype = C.c_size_t
         L.fv1_step.argtypes = [P(HwProblem), P(HwBuffers), vp]
         L.hwfv1_run.argtypes = [P(HwProblem), P(HwBuffers), vp, C.c_int64,
                                 P(HwStats), vp]
@@ -268,6 +271,17 @@ def mra_flag(problem, buffers, stream=None):
 
 def mra_traverse_leaves(problem, buffers, stream=None):
     _check(lib().mra_traverse_leaves(C.byref(problem), C.byref(buffers.c), _stream(stream)))
+
+
+def mra_traverse_leaves_noalloc(problem, buffers, stream=None):
+    """Traversal without a workspace (scratch in a per-GPU library array,
+    levels up to 11); buffers may be a Buffers object or an HwBuffers."""
+    c = buffers.c if hasattr(buffers, "c") else buffers
+    _check(lib().mra_traverse_leaves_noalloc(C.byref(problem), C.byref(c), _stream(stream)))
+
+
+def noalloc_scratch_bytes():
+    return int(lib().hw_noalloc_scratch_bytes())
 
 
 def fv1_step(problem, buffers, stream=None):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -481,6 +482,83 @@ int fill_stats(hw_plan* pl, const std::vector<uint64_t>& step0, hw_stats* stats,
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of the traversal variant that allocates nothing
+// ---------------------------------------------------------------------------
+// mra_traverse_leaves_noalloc keeps what mra_traverse_leaves keeps in the
+// caller's workspace (descriptor, per-workgroup leaf counts and offsets,
+// walk codes, fill table and leaf-level map) in one array per GPU instead,
+// sized for the largest level it accepts.
+namespace {
+
+constexpr int kNoAllocMaxL = 11;
+
+constexpr size_t ce_align(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct TravScratch {
+    size_t desc, tcount, big_src, gcode, lmap, total;
+};
+
+constexpr TravScratch trav_scratch_layout(int L)
+{
+    const size_t N = size_t(1) << (2 * L);
+    const size_t groups = size_t(1) << (2 * (L >= 2 ? L - 2 : 0));
+    const size_t ntrav = (groups + hw::kBlock - 1) / hw::kBlock;
+    TravScratch t{};
+    size_t o = 0;
+    t.desc = o;
+    o = ce_align(o + sizeof(Desc));
+    t.tcount = o;
+    o = ce_align(o + (ntrav + 1) * sizeof(uint32_t));
+    t.big_src = o;
+    o = ce_align(o + groups * sizeof(uint32_t));
+    t.gcode = o;
+    o = ce_align(o + groups);
+    t.lmap = o;
+    o = ce_align(o + N);
+    t.total = o;
+    return t;
+}
+
+constexpr size_t kScratchBytes = trav_scratch_layout(kNoAllocMaxL).total;
+
+}  // namespace
+
+// One copy per GPU, alive until the process ends.  Host code never uses
+// this name as an address: it takes the device address that
+// hipGetSymbolAddress returns for the current device (scratch_base).
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device, looked up once
+// per device (with that device current) and kept.
+int scratch_base(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(HW_EINVAL, "device %d is beyond the %d devices the library tracks", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(HW_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return HW_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* hw_last_error(void) { return g_err.c_str(); }
@@ -581,6 +659,53 @@ int mra_traverse_leaves(const hw_problem* p, const hw_buffers* b, hipStream_t st
     if (rc) return rc;
     const Desc* dd = work_desc(b);
     hipError_t e = hw::launch_traverse(Launch{dd, nullptr, 1}, n_trav(p->L), stream);
+    if (e != hipSuccess) return hip_fail(e, "traverse launch");
+    return ok();
+}
+
+size_t hw_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int mra_traverse_leaves_noalloc(const hw_problem* p, const hw_buffers* b,
+                                hipStream_t stream)
+{
+    int rc = check_problem(p);
+    if (rc) return rc;
+    if (p->L > kNoAllocMaxL)
+        return fail(HW_ECAPACITY,
+                    "L = %d: mra_traverse_leaves_noalloc holds levels up to %d "
+                    "(%zu bytes of scratch per GPU); use mra_traverse_leaves",
+                    p->L, kNoAllocMaxL, kScratchBytes);
+    if (!b) return fail(HW_EINVAL, "buffers is NULL");
+    const void* ptrs[] = {b->sig, b->leaves, b->scal};
+    const char* names[] = {"sig", "leaves", "scal"};
+    for (int k = 0; k < 3; ++k) {
+        if (!ptrs[k]) return fail(HW_EINVAL, "buffer %s is NULL", names[k]);
+        if (!aligned(ptrs[k]))
+            return fail(HW_EINVAL, "buffer %s is not 256-byte aligned", names[k]);
+    }
+    void* base = nullptr;
+    rc = scratch_base(&base);
+    if (rc) return rc;
+    // Descriptor with the traversal's scratch arrays in the per-GPU array;
+    // nothing else of the workspace is touched by the traversal kernels.
+    hw_buffers bb = *b;
+    bb.work = base;
+    Desc d = make_desc(p, &bb, nullptr);
+    const TravScratch t = trav_scratch_layout(p->L);
+    char* sb = static_cast<char*>(base);
+    d.tcount = reinterpret_cast<uint32_t*>(sb + t.tcount);
+    d.big_src = reinterpret_cast<uint32_t*>(sb + t.big_src);
+    d.gcode = reinterpret_cast<uint8_t*>(sb + t.gcode);
+    d.lmap = reinterpret_cast<uint8_t*>(sb + t.lmap);
+    d.wet = nullptr;
+    d.hist = nullptr;
+    d.dryb = nullptr;
+    d.bpart = nullptr;
+    d.partials = nullptr;
+    Desc* dd = reinterpret_cast<Desc*>(sb + t.desc);
+    hipError_t e = hw::launch_set_desc(d, dd, stream);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    e = hw::launch_traverse(Launch{dd, nullptr, 1}, n_trav(p->L), stream);
     if (e != hipSuccess) return hip_fail(e, "traverse launch");
     return ok();
 }
