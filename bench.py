@@ -38,8 +38,9 @@ def leaf_level_hist(buffers, L):
     return np.bincount(lvl, minlength=L + 1)
 
 
-def phase_bytes(L, w, hist, dry=None, uniform=False):
-    """Algorithmic HBM bytes of one step per phase (w = bytes per flow word).
+def phase_bytes(L, w, hist, dry=None, uniform=False, sparse=False, fv1_grid=2048):
+    """Algorithmic HBM bytes of one step per phase (w = bytes per flow word),
+    counting only what the step's kernels move.
 
     encode    read h, qx, qy on the finest level, write the coarse levels
               0..L-2 (the time loop does not store level L-1: its values are
@@ -47,8 +48,12 @@ def phase_bytes(L, w, hist, dry=None, uniform=False):
               static bed flags, write the raw flags; for L >= 5 also write
               one flag byte and a (mass, max |h|) pair per 64-cell block
     regularise read raw flags (one per cell, neighbours cached), write sig
-    traverse  read sig along the walk (one pass over the coarse flags per
-              kernel), write the leaf list and the fill table
+    traverse  count pass: read the flags of levels 0..L-1 once, write one
+              walk code per 16-cell group and one count per workgroup; the
+              emit pass runs only when some leaf is coarser than the finest
+              level: read the walk codes, write the leaf list, the fill
+              table (one word per group) and the leaf-level map (one byte
+              per finest cell)
     fv1       general step: per leaf its index, own h, qx, qy and bed (FP64),
               and the finest cells it writes (all descendants for leaves at
               or below the traversal group level, one otherwise).  A step
@@ -59,7 +64,11 @@ def phase_bytes(L, w, hist, dry=None, uniform=False):
               for L >= 5 every 64-cell block reads its flag byte, its history
               word and its (mass, max |h|) pair and writes the history word
               (neighbour flag bytes cached), and the wet table is written
-    fill      the finest cells of coarser leaves
+    fill      only when some leaf is coarser than a group: read the fill
+              table, write the finest cells of coarser leaves (with the
+              tree-sparse set, `sparse`, 64 cells of each 1024-cell span
+              below a leaf of level <= L-5)
+    finalize  read the partial records of both FV1 kernels (80 B each)
 
     uniform FV1 plan (FV1 and finalize only): every finest cell reads its
     depth (neighbours cached); the full update reads h, qx, qy and z and
@@ -70,6 +79,7 @@ def phase_bytes(L, w, hist, dry=None, uniform=False):
     Nc = (N - 1) // 3
     Lg = max(L - 2, 0)
     nl = int(hist.sum())
+    all_finest = int(hist[L]) == N
     fv1_writes = 0
     fill_writes = 0
     for m, cnt in enumerate(hist):
@@ -78,29 +88,39 @@ def phase_bytes(L, w, hist, dry=None, uniform=False):
             fv1_writes += cnt * 4 ** (L - m)
         else:
             fv1_writes += cnt
-            fill_writes += cnt * (4 ** (L - m) - 1)
+            if sparse and L >= 7 and m <= L - 5:
+                fill_writes += cnt * (4 ** (L - 5 - m) * 64 - 1)
+            else:
+                fill_writes += cnt * (4 ** (L - m) - 1)
     groups = 4 ** Lg
+    ntrav = (groups + 255) // 256
     blocks = N // 64 if L >= 5 else 0
+    finalize = 2 * fv1_grid * 80
     if uniform:
         stored, skipped = dry
         full = N - stored - skipped
         fv1 = full * (3 * w + 8 + 3 * w) + stored * 4 * w + skipped * w \
             + (N // 64) * 16 + 4 * (N // 512)
         return {"encode": 0, "regularise": 0, "traverse": 0, "fv1": int(fv1), "fill": 0,
-                "finalize": 0, "n_leaves": N}
+                "finalize": finalize, "n_leaves": N}
     fv1 = nl * (4 + 3 * w + 8) + 3 * w * fv1_writes
-    if dry is not None and int(hist[L]) == N:
+    if dry is not None and all_finest:
         stored, skipped = dry
         full = N - stored - skipped
         fv1 = full * (3 * w + 8 + 3 * w) + stored * 4 * w + blocks * (1 + 8 + 16 + 8) \
             + 4 * (N // 512)
+    traverse = Nc + groups + 4 * ntrav
+    fill = 0
+    if not all_finest:
+        traverse += groups + 4 * nl + 4 * groups + N
+        fill = 4 * groups + 3 * w * fill_writes
     return {
         "encode": 3 * w * N + 3 * w * (Nc - 4 ** (L - 1)) + 2 * Nc + blocks * (1 + 16),
         "regularise": 2 * Nc,
-        "traverse": 2 * Nc + 4 * nl + 4 * groups,
+        "traverse": traverse,
         "fv1": int(fv1),
-        "fill": 4 * groups + 3 * w * fill_writes,
-        "finalize": 0,
+        "fill": fill,
+        "finalize": finalize,
         "n_leaves": nl,
     }
 
@@ -157,11 +177,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def load_traffic(phase, precision):
-    """Measured HBM bytes per launch of a phase's kernels, from the committed
-    rocprofv3 counter summary, or None when there is none or the kernel
-    sources have changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{phase}_hydrograph_l12_{precision}.txt")
+def load_traffic(name):
+    """Measured HBM bytes from a committed rocprofv3 counter summary
+    profiles/<name>.txt: a dict of its key = value lines, or None when there
+    is none or the kernel sources have changed since the counters were
+    taken."""
+    path = os.path.join(ROOT, "profiles", name + ".txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -173,27 +194,50 @@ def load_traffic(phase, precision):
             kv[k.strip()] = v.strip()
     if kv.get("source_sha256") != kernel_source_hash():
         return None
-    return int(float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]))
+    return kv
 
 
-def roofline(res, L, w, precision=None):
-    pb = phase_bytes(L, w, res["hist"], res.get("dry"), res.get("uniform", False))
+def roofline(res, L, w, precision=None, workload=None, sparse=False):
+    """Dominant phase against the HBM roof (model bytes / HIP-event phase
+    time), its measured traffic when a current counter summary exists, and
+    the whole step: model bytes of every phase over the sum of the phase
+    times, and measured bytes per step over the same time when a current
+    whole-step counter summary exists."""
+    grid = (res.get("tuning") or {}).get("fv1_grid") or 2048
+    pb = phase_bytes(L, w, res["hist"], res.get("dry"), res.get("uniform", False),
+                     sparse=sparse, fv1_grid=grid)
     prof = {k: v for k, v in res["prof"].items() if v > 0}
     dom = max((k for k in prof), key=lambda k: prof[k])
     achieved = pb[dom] / (prof[dom] * 1e-3) / 1e9
     step_ms = sum(prof.values())
     total_bytes = sum(pb[k] for k in prof)
-    per_kernel = {k: {"ms": round(prof[k], 5),
+    per_kernel = {k: {"ms": round(prof[k], 5), "model_bytes": int(pb[k]),
                       "GBs": round(pb[k] / (prof[k] * 1e-3) / 1e9, 1) if prof[k] > 0 else None}
                   for k in prof}
+    traffic = None
+    step_measured = None
+    if precision and workload:
+        kv = load_traffic(f"traffic_{dom}_{workload}_{precision}")
+        if kv:
+            traffic = int(float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]))
+        kv = load_traffic(f"traffic_step_{workload}_{precision}")
+        if kv:
+            mb = float(kv["fetch_bytes_per_step"]) + float(kv["write_bytes_per_step"])
+            step_measured = {
+                "bytes": int(mb),
+                "frac": round(mb / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "model_over_measured": round(total_bytes / mb, 3),
+                "source": f"profiles/traffic_step_{workload}_{precision}.txt",
+            }
     return {
         "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": load_traffic(dom, precision) if precision else None,
+        "traffic": traffic,
         "algorithmic_bytes": int(pb[dom]),
         "avg_ms": round(prof[dom], 5),
-        "step_bytes": int(total_bytes), "step_ms_phases": round(step_ms, 5),
-        "step_frac": round(total_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step": {"model_bytes": int(total_bytes), "ms_phases": round(step_ms, 5),
+                 "frac": round(total_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "measured": step_measured},
         "phases": per_kernel,
     }
 
@@ -254,7 +298,24 @@ def bench_batch(hw, steps, warmup, n_members):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     lu1 = sum(s.scalars()["leaf_updates"] for s in sims)
+    s_mid = [s.scalars() for s in sims]
     prof = hw.hw_plan_profile(plan, 5)
+    s_end = [s.scalars() for s in sims]
+    pb = {}
+    for m, sim, a, b in zip(members, sims, s_mid, s_end):
+        hist = leaf_level_hist(sim.buffers, m.L)
+        dry = ((b["dry_stored"] - a["dry_stored"]) / 5.0,
+               (b["dry_skipped"] - a["dry_skipped"]) / 5.0)
+        for k, v in phase_bytes(m.L, 4, hist, dry,
+                                sparse=bool(best.get("encode_skip", 1) and best.get("fill_skip", 1)),
+                                fv1_grid=best.get("fv1_grid") or 2048).items():
+            if k != "n_leaves":
+                pb[k] = pb.get(k, 0) + v
+    pms = {k: v / 5 for k, v in prof.items() if v > 0}
+    dom = max(pms, key=lambda k: pms[k])
+    achieved = pb[dom] / (pms[dom] * 1e-3) / 1e9
+    step_ms = sum(pms.values())
+    step_bytes = sum(pb[k] for k in pms)
     levels = sorted(m.L for m in members)
     out = {
         "value": round(steps / (ms * 1e-3), 2), "unit": "ensemble timesteps/s",
@@ -264,6 +325,14 @@ def bench_batch(hw, steps, warmup, n_members):
         "ms_per_step": round(ms / steps, 4), "dtype": "f32 (FP64 significance)",
         "levels": {str(L): levels.count(L) for L in sorted(set(levels))},
         "phase_ms": {k: round(v / 5, 4) for k, v in prof.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes": int(pb[dom]), "avg_ms": round(pms[dom], 5),
+                     "step": {"model_bytes": int(step_bytes), "ms_phases": round(step_ms, 5),
+                              "frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                     "note": "model bytes summed over the members (their leaf levels and "
+                             "dry-pass counts after the timed steps), 5 profiled steps"},
         "tuning": best, "autotune_ms_per_step": table,
     }
     plan.close()
@@ -429,18 +498,142 @@ def bench_pseudo2d(hw, levels=(8, 9, 10, 11), epss=(1e-4, 1e-3, 1e-2), window=2.
             "precision": "fp64", "window_s": window, "rows": rows}
 
 
-def cpu_baseline(w, n_steps):
+def host_cpu():
+    """Host CPU model and logical CPU count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
+def time_oracle(w, n_steps):
     import oracle as O
-    log(f"[bench] cpu oracle: {n_steps} steps of {w.name}")
     o = O.Oracle(w.params, w.h, w.qx, w.qy, w.z)
     t0 = time.perf_counter()
     n = o.run(n_steps)
     dt = time.perf_counter() - t0
-    return {"value": round(n / dt, 4), "unit": "timesteps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"first {n} timesteps of {w.name} (L={w.L}, {4 ** w.L} cells), "
-                      f"FP64, single thread, {dt:.1f} s",
-            "leaf_updates_per_s": o.scalars()["leaf_updates"] / dt}
+    lu = o.scalars()["leaf_updates"]
+    o.close()
+    return n, dt, lu
+
+
+def cpu_baseline(w, n_steps, c2_steps):
+    """The oracle (one thread) on bounded samples: the headline workload's
+    first n_steps, the L = 6 dam break over bumps in full, and the first
+    c2_steps of the L = 10 circular dam break."""
+    import workloads as W
+    log(f"[bench] cpu oracle: {n_steps} steps of {w.name}")
+    n, dt, lu = time_oracle(w, n_steps)
+    out = {"value": round(n / dt, 4), "unit": "timesteps/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"first {n} timesteps of {w.name} (L={w.L}, {4 ** w.L} cells), "
+                     f"FP64, single thread, {dt:.1f} s",
+           "leaf_updates_per_s": lu / dt, "host": host_cpu(), "other": {}}
+    for ww, k in ((W.dambreak_bumps_l6(), 10 ** 6), (W.circular_dambreak_l10(), c2_steps)):
+        n, dt, lu = time_oracle(ww, k)
+        log(f"[bench] cpu oracle: {ww.name} {n} steps in {dt:.2f} s")
+        out["other"][ww.name] = {"steps": n, "s": round(dt, 3),
+                                 "timesteps_per_s": round(n / dt, 3),
+                                 "leaf_updates_per_s": lu / dt,
+                                 "complete_run": ww.n_steps <= n}
+    return out
+
+
+def whole_run(hw, w, precision, tuning):
+    """Every step of the workload's run from its initial state (HIP events
+    around all w.n_steps replays of the captured step), so that the wet
+    phase's full FV1 updates count as well as the dry start."""
+    import numpy as np
+    import torch
+    sim = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision=precision)
+    plan = hw.Plan([sim.problem], [sim.buffers], tuning=tuning)
+    hw.hwfv1_run(sim.problem, sim.buffers, 1, plan=plan, stats=False)
+    dev = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1), device="cuda")
+           for a in (w.h, w.qx, w.qy, w.z)]
+    hw.hw_ingest(sim.problem, sim.buffers, *dev)
+    del dev
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hw.hwfv1_run(sim.problem, sim.buffers, w.n_steps, plan=plan, stats=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    s = sim.scalars()
+    out = {"steps": int(s["step"]), "t_end_s": s["t"], "ms": round(ms, 3),
+           "ms_per_step": round(ms / w.n_steps, 5),
+           "value": round(w.n_steps / (ms * 1e-3), 2), "unit": "timesteps/s",
+           "leaf_updates": int(s["leaf_updates"]),
+           "full_updates": int(s["leaf_updates"] - s["dry_stored"] - s["dry_skipped"]),
+           "dry_pass_updates": int(s["dry_stored"] + s["dry_skipped"]),
+           "wet_cells_at_end": int((hw.hw_export(sim.problem, sim.buffers)[0]
+                                    > w.params["h_tol"]).sum().item())}
+    plan.close()
+    sim.close()
+    return out
+
+
+def precision_stress(hw, steps, prof_steps):
+    """The thin-sheet workload at L = 13 (eps 1e-4, rain, Manning 0.05, 500 m
+    relief): FP64 and FP32 bulk over the same steps; timesteps/s, rooflines,
+    and the FP32 form's error against FP64 (whose first steps the parity
+    tests compare with the oracle)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    log("[bench] precision stress: generating the L = 13 sheet-flow inputs")
+    w = W.sheetflow_l13(n_steps=steps)
+    out = {"workload": w.name, "L": w.L, "eps": w.params["eps"], "steps": steps}
+    res = {}
+    for prec in ("fp64", "fp32_bulk"):
+        r = time_single(hw, w, prec, steps, 2, prof_steps)
+        res[prec] = r
+        out[prec] = {"value": round(steps / (r["ms"] * 1e-3), 2), "unit": "timesteps/s",
+                     "ms_per_step": round(r["ms"] / steps, 5),
+                     "n_leaves": int(r["scalars"]["n_leaves"]),
+                     "leaf_updates_per_step": dry_split(r),
+                     "roofline": roofline(r, w.L, 8 if prec == "fp64" else 4),
+                     "mass": r["scalars"]["mass"], "mass0": r["scalars"]["mass0"],
+                     "t": r["scalars"]["t"], "tuning": r["tuning"]}
+        if prec == "fp64":
+            # keep only the exported fields of the FP64 run on the host
+            res["f64"] = [t.cpu().numpy() for t in hw.hw_export(r["sim"].problem, r["sim"].buffers)]
+            res["leaves64"] = r["sim"].buffers.leaf_list()
+            r["plan"].close()
+            r["sim"].close()
+            del r
+            res.pop("fp64")
+            torch.cuda.empty_cache()
+    r32 = res["fp32_bulk"]
+    b = [t.cpu().numpy() for t in hw.hw_export(r32["sim"].problem, r32["sim"].buffers)]
+    a = res["f64"]
+    l32 = r32["sim"].buffers.leaf_list()
+    out["error_fp32_vs_fp64"] = {
+        "l1_h": float(np.mean(np.abs(a[0] - b[0]))),
+        "linf_h": float(np.max(np.abs(a[0] - b[0]))),
+        "l1_qx": float(np.mean(np.abs(a[1] - b[1]))),
+        "linf_qx": float(np.max(np.abs(a[1] - b[1]))),
+        "l1_qy": float(np.mean(np.abs(a[2] - b[2]))),
+        "linf_qy": float(np.max(np.abs(a[2] - b[2]))),
+        "leaf_symdiff": int(len(np.setxor1d(res["leaves64"], l32))),
+        "n_leaves_fp64": int(len(res["leaves64"])),
+        "mass_rel_err": (out["fp32_bulk"]["mass"] - out["fp64"]["mass"]) / out["fp64"]["mass"],
+        "vs": "FP64 GPU run of the same steps (its first steps equal the oracle within 1e-10)",
+    }
+    log(f"[bench] precision stress: FP64 {out['fp64']['value']} steps/s, FP32 bulk "
+        f"{out['fp32_bulk']['value']} steps/s, {out['error_fp32_vs_fp64']}")
+    r32["plan"].close()
+    r32["sim"].close()
+    del r32, res
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -449,7 +642,11 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--prof-steps", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-c2-steps", type=int, default=50)
+    ap.add_argument("--stress-steps", type=int, default=1000)
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the L = 13 precision-stress runs")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-members", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
@@ -546,7 +743,7 @@ def main():
         "leaf_updates_per_s": r64["leaf_updates"] / (r64["ms"] * 1e-3),
         "n_leaves": int(r64["scalars"]["n_leaves"]),
         "leaf_updates_per_step": dry_split(r64),
-        "roofline": roofline(r64, L, 8, "fp64"),
+        "roofline": roofline(r64, L, 8, "fp64", w.name),
         "tuning": r64["tuning"], "autotune_ms_per_step": r64["tuning_table"],
     }
     if not args.no_variants:
@@ -577,12 +774,28 @@ def main():
             "n_leaves": int(rw["scalars"]["n_leaves"]),
             "wet_fraction": float((h_end > ww.params["h_tol"]).float().mean().item()),
             "leaf_updates_per_step": dry_split(rw),
-            "roofline": roofline(rw, L, 8),
+            "roofline": roofline(rw, L, 8, "fp64", ww.name),
             "tuning": rw["tuning"],
         }
         rw["plan"].close()
         rw["sim"].close()
         del rw, h_end
+        if not args.no_fp32:
+            rw = time_single(hw, ww, "fp32_bulk", ww.n_steps, 5, args.prof_steps, tuning)
+            line["fully_wet"]["fp32_bulk"] = {
+                "value": round(ww.n_steps / (rw["ms"] * 1e-3), 2), "unit": "timesteps/s",
+                "ms_per_step": round(rw["ms"] / ww.n_steps, 5),
+                "leaf_updates_per_step": dry_split(rw),
+                "roofline": roofline(rw, L, 4, "fp32_bulk", ww.name),
+                "tuning": rw["tuning"],
+            }
+            rw["plan"].close()
+            rw["sim"].close()
+            del rw
+        # The whole hydrograph run from t = 0 (dry start, then the wet phase).
+        line["whole_run"] = dict(whole_run(hw, w, "fp64", r64["tuning"]), workload=w.name,
+                                 precision="fp64")
+        log(f"[bench] whole run: {line['whole_run']}")
     if not args.no_speedup:
         # The same workload and steps on the uniform FV1 plan (every finest
         # cell updated, no multiresolution phases).
@@ -611,7 +824,7 @@ def main():
             "ms_per_step": round(r32["ms"] / args.steps, 5),
             "leaf_updates_per_s": r32["leaf_updates"] / (r32["ms"] * 1e-3),
             "leaf_updates_per_step": dry_split(r32),
-            "roofline": roofline(r32, L, 4, "fp32_bulk"),
+            "roofline": roofline(r32, L, 4, "fp32_bulk", w.name),
             "tuning": r32["tuning"],
             "error_vs_fp64": fp32_error(hw, r64, r32),
         }
@@ -622,6 +835,8 @@ def main():
     r64["sim"].close()
     del r64
     torch.cuda.empty_cache()
+    if not args.no_stress:
+        line["precision_stress"] = precision_stress(hw, args.stress_steps, min(args.prof_steps, 5))
     if not args.no_batch:
         line["batched"] = bench_batch(hw, args.batch_steps, args.warmup,
                                       args.batch_members)
@@ -635,7 +850,7 @@ def main():
         line["copy_calibration_bytes"] = {"read": n * 8, "write": n * 8}
         del src, dst
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.cpu_c2_steps)
     print(json.dumps(line), flush=True)
 
 

@@ -100,6 +100,12 @@ enum { HW_W = 0, HW_E = 1, HW_S = 2, HW_N = 3 };
  *               triangular hydrograph Q(t) rising to q_peak (m^3/s) at
  *               t_peak and back to 0 at t_base
  *   t_end       end time (s); +inf for a fixed number of steps
+ *   zsmax       s_max of the bed (Section 2.1.2: the largest bed
+ *               coefficient of the finest level), >= 0; 0 takes
+ *               max(1, max |z|) over the whole grid at ingest.  A domain
+ *               padded to the square grid passes the value of its own
+ *               cells, so that the padding's high ground does not change
+ *               the normalisation of the bed details inside the domain
  */
 typedef struct hw_problem {
     int32_t L;
@@ -110,6 +116,7 @@ typedef struct hw_problem {
     double manning_n, rain_rate;
     double inlet_y0, inlet_y1, q_peak, t_peak, t_base;
     double t_end;
+    double zsmax;
 } hw_problem;
 
 /*

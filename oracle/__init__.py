@@ -32,6 +32,7 @@ class OracleProblem(C.Structure):
         ("rain_rate", C.c_double), ("inlet_y0", C.c_double),
         ("inlet_y1", C.c_double), ("q_peak", C.c_double),
         ("t_peak", C.c_double), ("t_base", C.c_double), ("t_end", C.c_double),
+        ("zsmax", C.c_double),
     ]
 
 
@@ -113,6 +114,7 @@ def make_problem(params: dict) -> OracleProblem:
     p.t_peak = float(params.get("t_peak", 1.0))
     p.t_base = float(params.get("t_base", 2.0))
     p.t_end = float(params.get("t_end", math.inf))
+    p.zsmax = float(params.get("zsmax", 0.0))
     return p
 
 

@@ -292,6 +292,7 @@ oracle_state* oracle_create(const oracle_problem* p, const double* h,
                             const double* z)
 {
     if (!p || p->L < 1 || p->L > ORACLE_MAX_L || !(p->eps >= 0.0)) return NULL;
+    if (!(p->zsmax >= 0.0) || !isfinite(p->zsmax)) return NULL;
     oracle_state* st = calloc(1, sizeof(oracle_state));
     if (!st) return NULL;
     st->p = *p;
@@ -304,8 +305,11 @@ oracle_state* oracle_create(const oracle_problem* p, const double* h,
     memcpy(st->s[1][L], qx, N * sizeof(double));
     memcpy(st->s[2][L], qy, N * sizeof(double));
     memcpy(st->s[3][L], z, N * sizeof(double));
-    /* Static bed: encode once and keep its significance flags. */
-    st->smax[3] = guarded_smax(st->s[3][L], N);
+    /* Static bed: encode once and keep its significance flags.  s_max of
+     * the bed is the largest finest coefficient of the domain: over the
+     * whole grid, unless the caller gives the value of a domain that was
+     * padded to the square grid. */
+    st->smax[3] = p->zsmax > 0.0 ? p->zsmax : guarded_smax(st->s[3][L], N);
     encode_variable(st, 3, st->zraw);
     double maxspeed = 0.0;
     for (size_t k = 0; k < N; ++k) {

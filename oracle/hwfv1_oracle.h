@@ -52,6 +52,10 @@ typedef struct oracle_problem {
     double inlet_y0, inlet_y1;     /* west-edge inflow segment (m)        */
     double q_peak, t_peak, t_base; /* triangular hydrograph (m^3/s, s, s) */
     double t_end;         /* simulation end time (s); +inf for none        */
+    double zsmax;         /* s_max of the bed when > 0 (the largest bed
+                             coefficient of the domain's own finest cells,
+                             for a domain padded to the square grid); 0:
+                             max(1, max |z|) over the grid                 */
 } oracle_problem;
 
 typedef struct oracle_state oracle_state;

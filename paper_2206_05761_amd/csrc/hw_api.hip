@@ -161,6 +161,8 @@ int check_problem(const hw_problem* p)
         return fail(HW_EINVAL, "manning_n must be finite and >= 0");
     if (!std::isfinite(p->rain_rate)) return fail(HW_EINVAL, "rain_rate must be finite");
     if (!(p->t_end > 0.0)) return fail(HW_EINVAL, "t_end must be > 0 (or +inf)");
+    if (!std::isfinite(p->zsmax) || p->zsmax < 0.0)
+        return fail(HW_EINVAL, "zsmax must be finite and >= 0");
     if (!std::isfinite(p->q_peak) || p->q_peak < 0.0)
         return fail(HW_EINVAL, "q_peak must be finite and >= 0");
     if (p->q_peak > 0.0) {
@@ -224,6 +226,7 @@ Desc make_desc(const hw_problem* p, const hw_buffers* b, double* partials)
     d.t_peak = p->t_peak;
     d.t_base = p->t_base;
     d.t_end = p->t_end;
+    d.zsmax = p->zsmax;
     for (int s = 0; s < 2; ++s)
         for (int v = 0; v < 3; ++v) d.fine[s][v] = b->fine[s][v];
     for (int v = 0; v < 3; ++v) d.coarse[v] = b->coarse[v];

@@ -24,6 +24,7 @@ struct Desc {
     int32_t write_skip;    // FV1 may skip stores of unchanged dry blocks
     double eps, g, cfl, h_tol, dx, dy, dt_max, manning_n, rain_rate;
     double inlet_y0, inlet_y1, q_peak, t_peak, t_base, t_end;
+    double zsmax;          // bed s_max given by the caller (0: from the grid)
     void* fine[2][3];
     void* coarse[3];
     double* zhier;

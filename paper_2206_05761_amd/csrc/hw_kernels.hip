@@ -1995,7 +1995,7 @@ __global__ __launch_bounds__(kBlock) void k_ingest_final(const Desc* dd, int gri
         sc->smax[0] = tot[1] > 1.0 ? tot[1] : 1.0;
         sc->smax[1] = tot[2] > 1.0 ? tot[2] : 1.0;
         sc->smax[2] = tot[3] > 1.0 ? tot[3] : 1.0;
-        sc->smax[3] = tot[7] > 1.0 ? tot[7] : 1.0;
+        sc->smax[3] = d.zsmax > 0.0 ? d.zsmax : (tot[7] > 1.0 ? tot[7] : 1.0);
         sc->maxspeed = ms;
         for (int q = 0; q < 6; ++q) sc->acc[q] = 0.0;
         sc->step = 0;

@@ -16,6 +16,8 @@ Workloads (square 2^L x 2^L grids):
                            triangular west-edge inflow (500 m^3/s peak at
                            1800 s, base 3600 s) through a closed west edge,
                            other edges open, Manning 0.035, 2000 steps
+  hydrograph_wet_window    the hydrograph terrain and forcing from t0 = 1500 s
+                           with a pond 2 m deep at the inlet's centre (test)
   ensemble_64              64 members with L in {8..11}, eps in
                            {1e-4, 1e-3, 1e-2}, own fractal bed (relief 5-50 m),
                            dam-break or hydrograph forcing, Manning U(0.01,
@@ -166,6 +168,30 @@ def flooded_basin_l12(seed: int = 3, L: int = 12, n_steps: int = 200,
                     n_steps=n_steps, meta=dict(seed=seed))
 
 
+def hydrograph_wet_window(seed: int = 3, L: int = 12, t0: float = 1500.0,
+                          relief: float = 50.0) -> Workload:
+    """A wet window of the hydrograph run: its terrain, inflow and
+    boundaries, started at t0 (near the peak) with water already stored at
+    the inlet: a pond whose surface lies 2 m above the bed at the inlet's
+    centre, filling the bed below it within 2.5 km of the west edge and
+    2 km of the inlet's centre line, flowing east at 0.2 m/s.  Wet and dry
+    cells, a moving front and the inflow in one step (meta t0: the start
+    time both sides set)."""
+    w = hydrograph_l12(seed=seed, L=L, relief=relief)
+    length = 10_000.0
+    x, y = cell_centres(L, length)
+    z = w.z
+    n = 1 << L
+    j0 = min(n - 1, int(5000.0 / length * n))
+    eta0 = z[j0, 0] + 2.0
+    inside = (x < 2500.0) & (np.abs(y - 5000.0) < 2000.0)
+    h = np.where(inside, np.maximum(0.0, eta0 - z), 0.0)
+    qx = 0.2 * h
+    zero = np.zeros_like(h)
+    return Workload(f"hydrograph_wet_window_l{L}", dict(w.params), h, qx, zero, z,
+                    n_steps=5, meta=dict(seed=seed, t0=t0, eta0=float(eta0)))
+
+
 def sheetflow_l13(seed: int = 5, L: int = 13, n_steps: int = 1000) -> Workload:
     length = 10_000.0
     p = base_params(L, length, 1e-4, manning_n=0.05, bc=("open",) * 4,
@@ -283,6 +309,9 @@ def pseudo2d_channel(L: int = 8, eps: float = 1e-3, t_end: float = 40.0) -> Work
     the hydrostatic reconstruction)."""
     w = pseudo2d_dambreak(L, eps, t_end)
     n = 1 << L
+    # s_max of the bed over the channel's own cells (the guard value 1 on
+    # this flat bed), not over the padding
+    w.params = dict(w.params, zsmax=max(1.0, float(np.abs(w.z[: n // 2]).max())))
     w.h[n // 2:, :] = 0.0
     w.z[n // 2:, :] = 1000.0
     w.name = f"pseudo2d_channel_l{L}"
@@ -306,7 +335,8 @@ def humps_lake_at_rest(profile: str, L: int = 8, eps: float = 1e-3,
       rectangular  square blocks of height 1.0, 1.95, 3 m and side 6, 6, 8 m.
     The basin is rows 0..ny-1 of the 2^L-cell-wide square grid (cell size
     70 / 2^L, ny = 30 m / cell rounded), the rows above are dry ground
-    1000 m above the water (a closed edge, like the walls)."""
+    1000 m above the water (a closed edge, like the walls); the bed's s_max
+    is that of the basin (params zsmax)."""
     eta = HUMP_ETA[profile]
     length = 70.0
     n = 1 << L
@@ -328,6 +358,9 @@ def humps_lake_at_rest(profile: str, L: int = 8, eps: float = 1e-3,
             r = np.hypot(x - cx, y - cy)
             z = np.maximum(z, top * np.maximum(0.0, 1.0 - r / rad))
     h = np.maximum(0.0, eta - z)
+    # s_max of the bed over the basin's own cells (3 m, the highest hump),
+    # not over the padding
+    p["zsmax"] = max(1.0, float(np.abs(z[:ny]).max()))
     z[ny:, :] = 1000.0
     h[ny:, :] = 0.0
     zero = np.zeros_like(h)
