@@ -669,6 +669,12 @@ def main():
                          "(eps 1e-3) from its initial state to t_end, with the "
                          "tree-sparse finest set on or off (--sparse), and print its time")
     ap.add_argument("--sparse", type=int, default=1, choices=(0, 1))
+    ap.add_argument("--run", default=None,
+                    choices=("hydrograph_l12", "flooded_basin_l12", "sheetflow_l13"),
+                    help="profiling mode: only time this workload (--steps after "
+                         "--warmup, --precision, default launch shapes or --tuning) "
+                         "and print its time and phase split")
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32_bulk"))
     ap.add_argument("--circular-steps", type=int, default=0, metavar="K",
                     help="with --circular: run only the first K steps, once "
                          "(for counter collection), instead of to t_end")
@@ -718,6 +724,18 @@ def main():
         tuning = dict(encode_cells_per_thread=vals[0], fv1_grid=vals[1])
         if len(vals) > 2:
             tuning.update(encode_skip=vals[2], fill_skip=vals[2])
+    if args.run is not None:
+        ww = getattr(W, args.run)()
+        r = time_single(hw, ww, args.precision, args.steps, args.warmup, args.prof_steps,
+                        tuning if tuning is not None else {})
+        wb = 8 if args.precision == "fp64" else 4
+        print(json.dumps({"workload": ww.name, "precision": args.precision,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": round(r["ms"] / args.steps, 5),
+                          "leaf_updates_per_step": dry_split(r),
+                          "roofline": roofline(r, ww.L, wb, args.precision, ww.name)}),
+              flush=True)
+        return
     w = W.hydrograph_l12()
     L = w.L
     r64 = time_single(hw, w, "fp64", args.steps, args.warmup, args.prof_steps, tuning)

@@ -1067,76 +1067,23 @@ __device__ inline Cell<T> load_fine(const Fv1Ctx<T>& x, uint32_t k)
     return c;
 }
 
-// The full FV1 update of one leaf (the heavy kernel's path; waves whose
-// leaves are all dry take fv1_dry_write instead, which gives the same result).
-// FIN: the problem's leaves are all finest this step, so the leaf and its
-// neighbours are finest cells and no leaf-level byte is needed.
-template <typename T, bool FIN>
-__device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
+// The rest of one leaf's FV1 update once its four face fluxes (F: the
+// x-flux (mass, normal, tangential momentum) of the east and west faces, G:
+// the y-flux of the north and south faces) and its own reconstructed depth
+// at each face are known: the Audusse bed-slope terms, forward Euler (Eq. 2)
+// with the level-m cell size, the sources, the write-back to the cnt finest
+// cells from f0 on in the other set, and the partial record.  inW: the leaf
+// has an in-domain west neighbour (no inflow through it).
+template <typename T>
+__device__ inline void fv1_finish(const Fv1Ctx<T>& x, int m, uint32_t c, bool inW,
+                                  const Cell<T>& own, const T FE[3], const T FW[3],
+                                  const T GN[3], const T GS[3], T hcE, T hcW, T hcN,
+                                  T hcS, double dxm, double dym, uint64_t f0,
+                                  uint32_t cnt, Acc& acc)
 {
-    const int L = x.L;
-    const int m = FIN ? L : level_of(idx);
-    const uint32_t c = idx - (uint32_t)level_off(m);
     const T g = (T)x.g;
     const T tol = (T)x.h_tol;
     const double dt = x.dt;
-    const double dxm = ldexp(x.dx, L - m);
-    const double dym = ldexp(x.dy, L - m);
-
-    const uint32_t lvmask = m > 0 ? (0xffffffffu >> (32 - 2 * m)) : 0u;
-    const uint32_t xm = 0x55555555u & lvmask, ym = 0xaaaaaaaau & lvmask;
-    const int sh = 2 * (L - m);
-    const bool inW = (c & xm) != 0, inE = (c & xm) != xm;
-    const bool inS = (c & ym) != 0, inN = (c & ym) != ym;
-    const uint32_t cW = inW ? morton_xm(c, xm, ym) : c;
-    const uint32_t cE = inE ? morton_xp(c, xm, ym) : c;
-    const uint32_t cS = inS ? morton_ym(c, xm, ym) : c;
-    const uint32_t cN = inN ? morton_yp(c, xm, ym) : c;
-    const int lW = FIN ? L : x.lmap[(uint64_t)cW << sh];
-    const int lE = FIN ? L : x.lmap[(uint64_t)cE << sh];
-    const int lS = FIN ? L : x.lmap[(uint64_t)cS << sh];
-    const int lN = FIN ? L : x.lmap[(uint64_t)cN << sh];
-    const Cell<T> own = FIN ? load_fine<T>(x, c) : load_cell<T>(x, m, c);
-    const Cell<T> sW = FIN ? load_fine<T>(x, cW) : load_cell<T>(x, m, cW);
-    const Cell<T> sE = FIN ? load_fine<T>(x, cE) : load_cell<T>(x, m, cE);
-    const Cell<T> sS = FIN ? load_fine<T>(x, cS) : load_cell<T>(x, m, cS);
-    const Cell<T> sN = FIN ? load_fine<T>(x, cN) : load_cell<T>(x, m, cN);
-    const Cell<T> w = inW ? neighbour_fix<T>(x, m, cW, lW, sW) : ghost_cell<T>(x, HW_W, own);
-    const Cell<T> e = inE ? neighbour_fix<T>(x, m, cE, lE, sE) : ghost_cell<T>(x, HW_E, own);
-    const Cell<T> so = inS ? neighbour_fix<T>(x, m, cS, lS, sS) : ghost_cell<T>(x, HW_S, own);
-    const Cell<T> no = inN ? neighbour_fix<T>(x, m, cN, lN, sN) : ghost_cell<T>(x, HW_N, own);
-    const int sh2 = sh;
-    const uint64_t f0 = (uint64_t)c << sh2;
-    const uint32_t cnt = m >= x.Lg ? (1u << sh2) : 1u;
-
-    // Velocities only matter on faces with a wet side; a wave whose five
-    // states are all dry skips the divisions (values stay 0 and unused).
-    T uc = T(0), vc = T(0), uw = T(0), vw = T(0), ue = T(0), ve = T(0);
-    T us = T(0), vs = T(0), un = T(0), vn = T(0);
-    const bool wet = own.h > tol || w.h > tol || e.h > tol || so.h > tol || no.h > tol;
-    if (wave_any(wet)) {
-        const T rc = inv_depth(own.h, tol), rw = inv_depth(w.h, tol);
-        const T re = inv_depth(e.h, tol), rs = inv_depth(so.h, tol);
-        const T rn = inv_depth(no.h, tol);
-        uc = own.qx * rc;
-        vc = own.qy * rc;
-        uw = w.qx * rw;
-        vw = w.qy * rw;
-        ue = e.qx * re;
-        ve = e.qy * re;
-        us = so.qx * rs;
-        vs = so.qy * rs;
-        un = no.qx * rn;
-        vn = no.qy * rn;
-    }
-
-    T FE[3], FW[3], GN[3], GS[3];
-    T hcE, hcW, hcN, hcS, unused;
-    face_flux<T>(own.h, uc, vc, own.z, e.h, ue, ve, e.z, g, tol, FE, hcE, unused);
-    face_flux<T>(w.h, uw, vw, w.z, own.h, uc, vc, own.z, g, tol, FW, unused, hcW);
-    face_flux<T>(own.h, vc, uc, own.z, no.h, vn, un, no.z, g, tol, GN, hcN, unused);
-    face_flux<T>(so.h, vs, us, so.z, own.h, vc, uc, own.z, g, tol, GS, unused, hcS);
-
     // Audusse bed-slope term: own-depth pressure minus reconstructed-depth
     // pressure on each face, added to the normal momentum flux.
     const T hg = T(0.5) * g;
@@ -1198,6 +1145,202 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
         acc.v[6] = 1.0;
 }
 
+// The full FV1 update of one leaf (the heavy kernel's path; waves whose
+// leaves are all dry take fv1_dry_write instead, which gives the same result).
+// FIN: the problem's leaves are all finest this step, so the leaf and its
+// neighbours are finest cells and no leaf-level byte is needed.
+template <typename T, bool FIN>
+__device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
+{
+    const int L = x.L;
+    const int m = FIN ? L : level_of(idx);
+    const uint32_t c = idx - (uint32_t)level_off(m);
+    const T g = (T)x.g;
+    const T tol = (T)x.h_tol;
+    const double dxm = ldexp(x.dx, L - m);
+    const double dym = ldexp(x.dy, L - m);
+
+    const uint32_t lvmask = m > 0 ? (0xffffffffu >> (32 - 2 * m)) : 0u;
+    const uint32_t xm = 0x55555555u & lvmask, ym = 0xaaaaaaaau & lvmask;
+    const int sh = 2 * (L - m);
+    const bool inW = (c & xm) != 0, inE = (c & xm) != xm;
+    const bool inS = (c & ym) != 0, inN = (c & ym) != ym;
+    const uint32_t cW = inW ? morton_xm(c, xm, ym) : c;
+    const uint32_t cE = inE ? morton_xp(c, xm, ym) : c;
+    const uint32_t cS = inS ? morton_ym(c, xm, ym) : c;
+    const uint32_t cN = inN ? morton_yp(c, xm, ym) : c;
+    const int lW = FIN ? L : x.lmap[(uint64_t)cW << sh];
+    const int lE = FIN ? L : x.lmap[(uint64_t)cE << sh];
+    const int lS = FIN ? L : x.lmap[(uint64_t)cS << sh];
+    const int lN = FIN ? L : x.lmap[(uint64_t)cN << sh];
+    const Cell<T> own = FIN ? load_fine<T>(x, c) : load_cell<T>(x, m, c);
+    const Cell<T> sW = FIN ? load_fine<T>(x, cW) : load_cell<T>(x, m, cW);
+    const Cell<T> sE = FIN ? load_fine<T>(x, cE) : load_cell<T>(x, m, cE);
+    const Cell<T> sS = FIN ? load_fine<T>(x, cS) : load_cell<T>(x, m, cS);
+    const Cell<T> sN = FIN ? load_fine<T>(x, cN) : load_cell<T>(x, m, cN);
+    const Cell<T> w = inW ? neighbour_fix<T>(x, m, cW, lW, sW) : ghost_cell<T>(x, HW_W, own);
+    const Cell<T> e = inE ? neighbour_fix<T>(x, m, cE, lE, sE) : ghost_cell<T>(x, HW_E, own);
+    const Cell<T> so = inS ? neighbour_fix<T>(x, m, cS, lS, sS) : ghost_cell<T>(x, HW_S, own);
+    const Cell<T> no = inN ? neighbour_fix<T>(x, m, cN, lN, sN) : ghost_cell<T>(x, HW_N, own);
+
+    // Velocities only matter on faces with a wet side; a wave whose five
+    // states are all dry skips the divisions (values stay 0 and unused).
+    T uc = T(0), vc = T(0), uw = T(0), vw = T(0), ue = T(0), ve = T(0);
+    T us = T(0), vs = T(0), un = T(0), vn = T(0);
+    const bool wet = own.h > tol || w.h > tol || e.h > tol || so.h > tol || no.h > tol;
+    if (wave_any(wet)) {
+        const T rc = inv_depth(own.h, tol), rw = inv_depth(w.h, tol);
+        const T re = inv_depth(e.h, tol), rs = inv_depth(so.h, tol);
+        const T rn = inv_depth(no.h, tol);
+        uc = own.qx * rc;
+        vc = own.qy * rc;
+        uw = w.qx * rw;
+        vw = w.qy * rw;
+        ue = e.qx * re;
+        ve = e.qy * re;
+        us = so.qx * rs;
+        vs = so.qy * rs;
+        un = no.qx * rn;
+        vn = no.qy * rn;
+    }
+
+    T FE[3], FW[3], GN[3], GS[3];
+    T hcE, hcW, hcN, hcS, unused;
+    face_flux<T>(own.h, uc, vc, own.z, e.h, ue, ve, e.z, g, tol, FE, hcE, unused);
+    face_flux<T>(w.h, uw, vw, w.z, own.h, uc, vc, own.z, g, tol, FW, unused, hcW);
+    face_flux<T>(own.h, vc, uc, own.z, no.h, vn, un, no.z, g, tol, GN, hcN, unused);
+    face_flux<T>(so.h, vs, us, so.z, own.h, vc, uc, own.z, g, tol, GS, unused, hcS);
+    fv1_finish<T>(x, m, c, inW, own, FE, FW, GN, GS, hcE, hcW, hcN, hcS, dxm, dym,
+                  (uint64_t)c << sh, m >= x.Lg ? (1u << sh) : 1u, acc);
+}
+
+// LDS of one wave's block update: the 8 x 8 cells of the block and their
+// 32 face neighbours on a 10 x 10 local grid (local (i + 1, j + 1) holds
+// block cell (i, j); corners unused), and the 72 x-faces and 72 y-faces
+// touching the block: per face the flux (mass, normal and tangential
+// momentum) and the two reconstructed depths.
+template <typename T>
+struct BlockLds {
+    T h[100], u[100], v[100];
+    double z[100];
+    T F[2][3][72];     // [x, y][component][face]
+    T hl[2][72], hr[2][72];
+};
+
+// Order LDS writes of the wave before its later LDS reads (the LDS executes
+// one wave's operations in order; this keeps the compiler from moving them).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The full FV1 update of the 64 finest leaves of one aligned 8 x 8 Morton
+// block (cells c0 .. c0 + 63 of a problem whose leaves are all finest,
+// L >= 3), by one wave.  The result is fv1_leaf's for each cell: every face
+// flux is the same call with the same arguments, made once per face instead
+// of once from each side (144 faces for 64 cells instead of 256), and each
+// cell's velocities are formed once instead of once per face that uses them.
+template <typename T>
+__device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, BlockLds<T>& s)
+{
+    const int L = x.L;
+    const uint32_t lane = threadIdx.x & (kWave - 1u);
+    const T g = (T)x.g;
+    const T tol = (T)x.h_tol;
+    const uint32_t side = 1u << L;
+    const uint32_t I0 = compact1by1(c0), J0 = compact1by1(c0 >> 1);
+    // own cell
+    const uint32_t c = c0 + lane;
+    const uint32_t bi = compact1by1(lane), bj = compact1by1(lane >> 1);
+    const Cell<T> own = load_fine<T>(x, c);
+    // the halo: lanes 0-7 west column, 8-15 east, 16-23 south row, 24-31
+    // north; beyond the domain edge the ghost of the adjacent block cell
+    Cell<T> hc = own;
+    int hidx = 0;
+    if (lane < 32u) {
+        const uint32_t k = lane & 7u;
+        const int dir = (int)(lane >> 3);   // HW_W, HW_E, HW_S, HW_N
+        uint32_t ei, ej;                    // adjacent block cell
+        int nI, nJ;                         // face neighbour (finest coordinates)
+        bool in;
+        if (dir == HW_W) {
+            ei = 0; ej = k; nI = (int)I0 - 1; nJ = (int)(J0 + k); in = I0 > 0u;
+            hidx = 10 * (int)(k + 1);
+        } else if (dir == HW_E) {
+            ei = 7; ej = k; nI = (int)I0 + 8; nJ = (int)(J0 + k); in = I0 + 8u < side;
+            hidx = 9 + 10 * (int)(k + 1);
+        } else if (dir == HW_S) {
+            ei = k; ej = 0; nI = (int)(I0 + k); nJ = (int)J0 - 1; in = J0 > 0u;
+            hidx = (int)(k + 1);
+        } else {
+            ei = k; ej = 7; nI = (int)(I0 + k); nJ = (int)J0 + 8; in = J0 + 8u < side;
+            hidx = (int)(k + 1) + 90;
+        }
+        const uint32_t src = in ? morton((uint32_t)nI, (uint32_t)nJ) : c0 + morton(ei, ej);
+        hc = load_fine<T>(x, src);
+        if (!in) hc = ghost_cell<T>(x, dir, hc);
+    }
+    {
+        const int me = (int)(bi + 1 + 10 * (bj + 1));
+        const T r = inv_depth(own.h, tol);
+        s.h[me] = own.h;
+        s.u[me] = own.qx * r;
+        s.v[me] = own.qy * r;
+        s.z[me] = own.z;
+    }
+    if (lane < 32u) {
+        const T r = inv_depth(hc.h, tol);
+        s.h[hidx] = hc.h;
+        s.u[hidx] = hc.qx * r;
+        s.v[hidx] = hc.qy * r;
+        s.z[hidx] = hc.z;
+    }
+    wave_lds_sync();
+    // faces: q < 72 the x-face between local (b, a) and (b + 1, a), else the
+    // y-face between local (a, b) and (a, b + 1), with a = 1 + q' / 9 and
+    // b = q' % 9 for q' = q mod 72
+#pragma unroll 1
+    for (uint32_t q = lane; q < 144u; q += kWave) {
+        const bool isx = q < 72u;
+        const uint32_t qq = isx ? q : q - 72u;
+        const int a = (int)(qq / 9u) + 1, b = (int)(qq % 9u);
+        const int il = isx ? b + 10 * a : a + 10 * b;
+        const int ir = isx ? il + 1 : il + 10;
+        const T unl = isx ? s.u[il] : s.v[il], utl = isx ? s.v[il] : s.u[il];
+        const T unr = isx ? s.u[ir] : s.v[ir], utr = isx ? s.v[ir] : s.u[ir];
+        T F[3], hls, hrs;
+        face_flux<T>(s.h[il], unl, utl, s.z[il], s.h[ir], unr, utr, s.z[ir], g, tol, F, hls,
+                     hrs);
+        const int d = isx ? 0 : 1;
+        s.F[d][0][qq] = F[0];
+        s.F[d][1][qq] = F[1];
+        s.F[d][2][qq] = F[2];
+        s.hl[d][qq] = hls;
+        s.hr[d][qq] = hrs;
+    }
+    wave_lds_sync();
+    // own faces: x-faces (bj, bi) east / (bj, bi - 1) west in rows of 9,
+    // y-faces likewise by column
+    const int qe = (int)(bj * 9u + bi + 1u), qw = (int)(bj * 9u + bi);
+    const int qn = (int)(bi * 9u + bj + 1u), qs = (int)(bi * 9u + bj);
+    T FE[3], FW[3], GN[3], GS[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        FE[k] = s.F[0][k][qe];
+        FW[k] = s.F[0][k][qw];
+        GN[k] = s.F[1][k][qn];
+        GS[k] = s.F[1][k][qs];
+    }
+    const T hcE = s.hl[0][qe], hcW = s.hr[0][qw];
+    const T hcN = s.hl[1][qn], hcS = s.hr[1][qs];
+    const bool inW = (I0 + bi) != 0u;
+    fv1_finish<T>(x, L, c, inW, own, FE, FW, GN, GS, hcE, hcW, hcN, hcS, x.dx, x.dy,
+                  (uint64_t)c, 1u, acc);
+    // the next block's LDS writes must not overtake this block's reads
+    wave_lds_sync();
+}
 
 // True when the west-edge inflow adds water to leaf (m, c) at time t.
 template <typename T>
@@ -1678,6 +1821,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
     __shared__ double red[kBlock / kWave][kPartial];
     __shared__ double rxy[2 * (HW_MAX_L + 1)];
     __shared__ const uint8_t* wtab[kMaxScen];
+    __shared__ BlockLds<T> blds[kBlock / kWave];
     const int tid = threadIdx.x;
     const int wid = tid / kWave;
     const int lane = tid & (kWave - 1);
@@ -1742,7 +1886,11 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
                 if ((k++ & (kBlock / kWave - 1)) != wid) continue;
                 const uint32_t w = (uint32_t)bit / kLeafBatch, u = (uint32_t)bit % kLeafBatch;
                 const uint32_t leaf = base + u * kBlock + w * kWave + (uint32_t)lane;
-                if (leaf < x.nl) {
+                if (finest && x.L >= 3) {
+                    // one aligned 8 x 8 block of finest leaves per wave
+                    const uint32_t c0 = base + u * kBlock + w * kWave;
+                    if (c0 < x.nl) fv1_block<T>(x, c0, acc, blds[wid]);
+                } else if (leaf < x.nl) {
                     if (finest) fv1_leaf<T, true>(x, fin_off + leaf, acc);
                     else fv1_leaf<T, false>(x, x.leaves[leaf], acc);
                 }

@@ -56,7 +56,10 @@ def _compare(hw, w, sim, o, steps):
     compare_leaf_lists(w.L, leaves, o.leaves(), oracle_tie_band(o), log)
     assert st["t"] == pytest.approx(so["t"], rel=1e-13)
     assert st["dt"] == pytest.approx(so["dt"], rel=1e-10)
-    assert st["mass"] == pytest.approx(so["mass"], rel=1e-12)
+    # The oracle adds the leaves' masses one after the other: with N nearly
+    # equal terms that sum's rounding error can reach N 2^-53 of the total
+    # (the bound of recursive summation); the GPU sums per block.
+    assert st["mass"] == pytest.approx(so["mass"], rel=max(1e-12, 4.0 ** w.L * 2.0 ** -53))
     return st, so, leaves
 
 
