@@ -729,6 +729,14 @@ def main():
         r = time_single(hw, ww, args.precision, args.steps, args.warmup, args.prof_steps,
                         tuning if tuning is not None else {})
         wb = 8 if args.precision == "fp64" else 4
+        if args.copy_calibration_mib > 0:
+            n = args.copy_calibration_mib * (1 << 20) // 8
+            src = torch.ones(n, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
         print(json.dumps({"workload": ww.name, "precision": args.precision,
                           "steps": args.steps, "warmup": args.warmup,
                           "ms_per_step": round(r["ms"] / args.steps, 5),

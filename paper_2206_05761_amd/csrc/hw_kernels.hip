@@ -915,6 +915,10 @@ __device__ inline void face_flux(T hl, T unl, T utl, double zl, T hr, T unr,
                                  T utr, double zr, T g, T tol, T F[3],
                                  T& hls_out, T& hrs_out)
 {
+    // FV1 arithmetic may contract a*b+c into one fused multiply-add (its
+    // parity bar is 1e-10, not bit identity; the encoding and the
+    // significance test stay uncontracted)
+#pragma clang fp contract(fast)
     const T dzl = (T)(zr - zl);
     const T dzr = (T)(zl - zr);
     T hls = hl - (dzl > T(0) ? dzl : T(0));
@@ -985,6 +989,10 @@ __device__ inline double inflow_rate(const Fv1Ctx<T>& x, double t)
 template <typename T>
 __device__ inline double wave_speed(T h, T qx, T qy, T ih, T g, T tol)
 {
+    // FV1 arithmetic may contract a*b+c into one fused multiply-add (its
+    // parity bar is 1e-10, not bit identity; the encoding and the
+    // significance test stay uncontracted)
+#pragma clang fp contract(fast)
     if (!(h > tol)) return 0.0;
     const T c = sqrt(g * h);
     const T u = qx * ih;
@@ -1081,6 +1089,10 @@ __device__ inline void fv1_finish(const Fv1Ctx<T>& x, int m, uint32_t c, bool in
                                   T hcS, double dxm, double dym, uint64_t f0,
                                   uint32_t cnt, Acc& acc)
 {
+    // FV1 arithmetic may contract a*b+c into one fused multiply-add (its
+    // parity bar is 1e-10, not bit identity; the encoding and the
+    // significance test stay uncontracted)
+#pragma clang fp contract(fast)
     const T g = (T)x.g;
     const T tol = (T)x.h_tol;
     const double dt = x.dt;
