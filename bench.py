@@ -513,14 +513,17 @@ def host_cpu():
 
 
 def time_oracle(w, n_steps):
+    """Oracle steps taken, seconds, leaf updates, and whether the workload's
+    run is complete (its step count or its end time reached)."""
     import oracle as O
     o = O.Oracle(w.params, w.h, w.qx, w.qy, w.z)
     t0 = time.perf_counter()
     n = o.run(n_steps)
     dt = time.perf_counter() - t0
-    lu = o.scalars()["leaf_updates"]
+    sc = o.scalars()
+    done = n >= w.n_steps or sc["t"] >= w.params.get("t_end", math.inf)
     o.close()
-    return n, dt, lu
+    return n, dt, sc["leaf_updates"], done
 
 
 def cpu_baseline(w, n_steps, c2_steps):
@@ -529,19 +532,19 @@ def cpu_baseline(w, n_steps, c2_steps):
     c2_steps of the L = 10 circular dam break."""
     import workloads as W
     log(f"[bench] cpu oracle: {n_steps} steps of {w.name}")
-    n, dt, lu = time_oracle(w, n_steps)
+    n, dt, lu, _ = time_oracle(w, n_steps)
     out = {"value": round(n / dt, 4), "unit": "timesteps/s", "cores": 1,
            "kind": "oracle",
            "sample": f"first {n} timesteps of {w.name} (L={w.L}, {4 ** w.L} cells), "
                      f"FP64, single thread, {dt:.1f} s",
            "leaf_updates_per_s": lu / dt, "host": host_cpu(), "other": {}}
     for ww, k in ((W.dambreak_bumps_l6(), 10 ** 6), (W.circular_dambreak_l10(), c2_steps)):
-        n, dt, lu = time_oracle(ww, k)
+        n, dt, lu, done = time_oracle(ww, k)
         log(f"[bench] cpu oracle: {ww.name} {n} steps in {dt:.2f} s")
         out["other"][ww.name] = {"steps": n, "s": round(dt, 3),
                                  "timesteps_per_s": round(n / dt, 3),
                                  "leaf_updates_per_s": lu / dt,
-                                 "complete_run": ww.n_steps <= n}
+                                 "complete_run": bool(done)}
     return out
 
 

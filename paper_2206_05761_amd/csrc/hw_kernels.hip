@@ -899,11 +899,51 @@ __device__ inline Cell<T> ghost_cell(const Fv1Ctx<T>& x, int dir, const Cell<T>&
     return g;
 }
 
+// Reciprocal of a finite x with 2^-1000 < |x| < 2^1000 (the FV1 update's
+// wet depths, HLL speed differences and friction denominators): the
+// hardware estimate refined by two Newton steps r += r (1 - x r), within
+// about an ulp of the correctly rounded quotient, at a third of the
+// instructions of the full division.  FP32: the hardware reciprocal (1 ulp).
+__device__ inline double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ inline float rcp_nr(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// x^(-1/3) for x > 0: a single-precision seed 2^(-log2(x) / 3) from the
+// hardware logarithm and exponential, then Newton steps for y^-3 = x,
+// y += y (1 - x y^3) / 3, each doubling the correct bits (two steps for
+// FP64, one for FP32); outside 1e-30 < x < 1e30, where the seed could
+// under- or overflow, 1 / cbrt(x).
+__device__ inline double inv_cbrt(double x)
+{
+    if (!(x > 1e-30 && x < 1e30)) return 1.0 / cbrt(x);
+    double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)x) *
+                                              (-1.0f / 3.0f));
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double e = fma(-x, y * y * y, 1.0);
+        y = fma(y * e, 1.0 / 3.0, y);
+    }
+    return y;
+}
+__device__ inline float inv_cbrt(float x)
+{
+    if (!(x > 1e-30f && x < 1e30f)) return 1.0f / cbrtf(x);
+    float y = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (-1.0f / 3.0f));
+    const float e = fmaf(-x, y * y * y, 1.0f);
+    return fmaf(y * e, 1.0f / 3.0f, y);
+}
+
 // 1/h for a wet depth, 0 for a dry one (velocities are then 0).
 template <typename T>
 __device__ inline T inv_depth(T h, T tol)
 {
-    return h > tol ? T(1) / h : T(0);
+    return h > tol ? rcp_nr(h) : T(0);
 }
 
 // One face between a left and a right state (normal velocity un, tangential
@@ -969,7 +1009,7 @@ __device__ inline void face_flux(T hl, T unl, T utl, double zl, T hr, T unr,
     } else {
         // one reciprocal of the speed difference serves the three components
         const T slsr = sl * sr;
-        const T inv = T(1) / (sr - sl);
+        const T inv = rcp_nr(sr - sl);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
             F[k] = ((sr * Fl[k] - sl * Fr[k]) + slsr * (Ur[k] - Ul[k])) * inv;
@@ -1135,8 +1175,8 @@ __device__ inline void fv1_finish(const Fv1Ctx<T>& x, int m, uint32_t c, bool in
     } else if (x.manning_n > 0.0) {
         const T nm = (T)x.manning_n;
         const T speed = sqrt(qx * qx + qy * qy) * ih;
-        const T cf = g * nm * nm / cbrt(h);
-        const T iden = T(1) / (T(1) + (T)dt * cf * speed * ih);
+        const T cf = g * nm * nm * inv_cbrt(h);
+        const T iden = rcp_nr(T(1) + (T)dt * cf * speed * ih);
         qx = qx * iden;
         qy = qy * iden;
     }
@@ -1248,6 +1288,56 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Per-lane constants of the block update (the same for every block): the
+// lane's cell in the block, its local-grid index and own faces, the faces
+// it computes (pass p: face lane + 64 p, p = 0..2, as below), and its halo
+// cell (lanes 0-31: side lane / 8, position lane % 8).
+struct BlockConst {
+    uint32_t bi, bj;       // own cell in the block
+    int me;                // own cell on the local grid
+    int fl[3];             // left cell of the lane's face in each pass
+    int fq[3];             // that face's index within its direction
+    int qe, qw, qn, qs;    // own east / west x-faces, north / south y-faces
+    int hidx;              // halo cell on the local grid
+    uint32_t ei, ej;       // block cell next to the halo cell
+    int di, dj;            // offset from that block cell to the halo cell
+};
+
+__device__ inline BlockConst block_const()
+{
+    BlockConst k;
+    const uint32_t lane = threadIdx.x & (kWave - 1u);
+    k.bi = compact1by1(lane);
+    k.bj = compact1by1(lane >> 1);
+    k.me = (int)(k.bi + 1 + 10 * (k.bj + 1));
+    // face q < 72: x-face between local (b, a) and (b + 1, a), else the
+    // y-face between (a, b) and (a, b + 1), with a = 1 + q' / 9 and
+    // b = q' % 9 for q' = q mod 72
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const uint32_t q = lane + 64u * (uint32_t)p;
+        const bool isx = q < 72u;
+        const uint32_t qq = isx ? q : q - 72u;
+        const int a = (int)(qq / 9u) + 1, b = (int)(qq % 9u);
+        k.fl[p] = isx ? b + 10 * a : a + 10 * b;
+        k.fq[p] = (int)qq;
+    }
+    k.qe = (int)(k.bj * 9u + k.bi + 1u);
+    k.qw = (int)(k.bj * 9u + k.bi);
+    k.qn = (int)(k.bi * 9u + k.bj + 1u);
+    k.qs = (int)(k.bi * 9u + k.bj);
+    const uint32_t h = lane & 7u;
+    const uint32_t dir = (lane >> 3) & 3u;   // HW_W, HW_E, HW_S, HW_N
+    const bool xdir = dir < 2u;
+    k.ei = xdir ? (dir == (uint32_t)HW_W ? 0u : 7u) : h;
+    k.ej = xdir ? h : (dir == (uint32_t)HW_S ? 0u : 7u);
+    k.di = dir == (uint32_t)HW_W ? -1 : dir == (uint32_t)HW_E ? 1 : 0;
+    k.dj = dir == (uint32_t)HW_S ? -1 : dir == (uint32_t)HW_N ? 1 : 0;
+    k.hidx = xdir ? (dir == (uint32_t)HW_W ? 0 : 9) + 10 * (int)(h + 1)
+                  : (int)(h + 1) + (dir == (uint32_t)HW_S ? 0 : 90);
+    return k;
+}
+
 // The full FV1 update of the 64 finest leaves of one aligned 8 x 8 Morton
 // block (cells c0 .. c0 + 63 of a problem whose leaves are all finest,
 // L >= 3), by one wave.  The result is fv1_leaf's for each cell: every face
@@ -1255,7 +1345,8 @@ __device__ inline void wave_lds_sync()
 // of once from each side (144 faces for 64 cells instead of 256), and each
 // cell's velocities are formed once instead of once per face that uses them.
 template <typename T>
-__device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, BlockLds<T>& s)
+__device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, BlockLds<T>& s,
+                                 const BlockConst& kc)
 {
     const int L = x.L;
     const uint32_t lane = threadIdx.x & (kWave - 1u);
@@ -1263,62 +1354,52 @@ __device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, Bloc
     const T tol = (T)x.h_tol;
     const uint32_t side = 1u << L;
     const uint32_t I0 = compact1by1(c0), J0 = compact1by1(c0 >> 1);
-    // own cell
     const uint32_t c = c0 + lane;
-    const uint32_t bi = compact1by1(lane), bj = compact1by1(lane >> 1);
+    // Halo (lanes 0-31): the face neighbour of the block cell (ei, ej), or
+    // beyond the domain edge that cell's ghost.  Every load of the block is
+    // issued before any is used (lanes 32-63 load their own cell a second
+    // time, unused).
+    const int nI = (int)(I0 + kc.ei) + kc.di;
+    const int nJ = (int)(J0 + kc.ej) + kc.dj;
+    const bool in = nI >= 0 && nI < (int)side && nJ >= 0 && nJ < (int)side;
+    const uint32_t src = lane >= 32u ? c
+                       : in ? morton((uint32_t)nI, (uint32_t)nJ) : c0 + morton(kc.ei, kc.ej);
     const Cell<T> own = load_fine<T>(x, c);
-    // the halo: lanes 0-7 west column, 8-15 east, 16-23 south row, 24-31
-    // north; beyond the domain edge the ghost of the adjacent block cell
-    Cell<T> hc = own;
-    int hidx = 0;
-    if (lane < 32u) {
-        const uint32_t k = lane & 7u;
-        const int dir = (int)(lane >> 3);   // HW_W, HW_E, HW_S, HW_N
-        uint32_t ei, ej;                    // adjacent block cell
-        int nI, nJ;                         // face neighbour (finest coordinates)
-        bool in;
-        if (dir == HW_W) {
-            ei = 0; ej = k; nI = (int)I0 - 1; nJ = (int)(J0 + k); in = I0 > 0u;
-            hidx = 10 * (int)(k + 1);
-        } else if (dir == HW_E) {
-            ei = 7; ej = k; nI = (int)I0 + 8; nJ = (int)(J0 + k); in = I0 + 8u < side;
-            hidx = 9 + 10 * (int)(k + 1);
-        } else if (dir == HW_S) {
-            ei = k; ej = 0; nI = (int)(I0 + k); nJ = (int)J0 - 1; in = J0 > 0u;
-            hidx = (int)(k + 1);
-        } else {
-            ei = k; ej = 7; nI = (int)(I0 + k); nJ = (int)J0 + 8; in = J0 + 8u < side;
-            hidx = (int)(k + 1) + 90;
+    Cell<T> hc = load_fine<T>(x, src);
+    __builtin_amdgcn_sched_barrier(0);
+    if (!in && lane < 32u) {
+        const int dir = (int)((lane >> 3) & 3u);
+        const bool wall = (dir == HW_W && x.bc[HW_W] == HW_BC_WALL) ||
+                          (dir == HW_E && x.bc[HW_E] == HW_BC_WALL) ||
+                          (dir == HW_S && x.bc[HW_S] == HW_BC_WALL) ||
+                          (dir == HW_N && x.bc[HW_N] == HW_BC_WALL);
+        if (wall) {
+            if (dir < 2) hc.qx = -hc.qx;
+            else hc.qy = -hc.qy;
         }
-        const uint32_t src = in ? morton((uint32_t)nI, (uint32_t)nJ) : c0 + morton(ei, ej);
-        hc = load_fine<T>(x, src);
-        if (!in) hc = ghost_cell<T>(x, dir, hc);
     }
     {
-        const int me = (int)(bi + 1 + 10 * (bj + 1));
         const T r = inv_depth(own.h, tol);
-        s.h[me] = own.h;
-        s.u[me] = own.qx * r;
-        s.v[me] = own.qy * r;
-        s.z[me] = own.z;
+        s.h[kc.me] = own.h;
+        s.u[kc.me] = own.qx * r;
+        s.v[kc.me] = own.qy * r;
+        s.z[kc.me] = own.z;
     }
     if (lane < 32u) {
         const T r = inv_depth(hc.h, tol);
-        s.h[hidx] = hc.h;
-        s.u[hidx] = hc.qx * r;
-        s.v[hidx] = hc.qy * r;
-        s.z[hidx] = hc.z;
+        s.h[kc.hidx] = hc.h;
+        s.u[kc.hidx] = hc.qx * r;
+        s.v[kc.hidx] = hc.qy * r;
+        s.z[kc.hidx] = hc.z;
     }
     wave_lds_sync();
-    // faces: q < 72 the x-face between local (b, a) and (b + 1, a), else the
-    // y-face between local (a, b) and (a, b + 1), with a = 1 + q' / 9 and
-    // b = q' % 9 for q' = q mod 72
-#pragma unroll 1
-    for (uint32_t q = lane; q < 144u; q += kWave) {
-        const bool isx = q < 72u;
-        const uint32_t qq = isx ? q : q - 72u;
-        const int a = (int)(qq / 9u) + 1, b = (int)(qq % 9u);
-        const int il = isx ? b + 10 * a : a + 10 * b;
+    // faces: pass 0 x-faces 0..63; pass 1 x-faces 64..71 (lanes 0-7) and
+    // y-faces 0..55; pass 2 y-faces 56..71 (lanes 0-15)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        if (p == 2 && lane >= 16u) break;
+        const bool isx = p == 0 || (p == 1 && lane < 8u);
+        const int il = kc.fl[p];
         const int ir = isx ? il + 1 : il + 10;
         const T unl = isx ? s.u[il] : s.v[il], utl = isx ? s.v[il] : s.u[il];
         const T unr = isx ? s.u[ir] : s.v[ir], utr = isx ? s.v[ir] : s.u[ir];
@@ -1326,6 +1407,7 @@ __device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, Bloc
         face_flux<T>(s.h[il], unl, utl, s.z[il], s.h[ir], unr, utr, s.z[ir], g, tol, F, hls,
                      hrs);
         const int d = isx ? 0 : 1;
+        const int qq = kc.fq[p];
         s.F[d][0][qq] = F[0];
         s.F[d][1][qq] = F[1];
         s.F[d][2][qq] = F[2];
@@ -1333,21 +1415,17 @@ __device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, Bloc
         s.hr[d][qq] = hrs;
     }
     wave_lds_sync();
-    // own faces: x-faces (bj, bi) east / (bj, bi - 1) west in rows of 9,
-    // y-faces likewise by column
-    const int qe = (int)(bj * 9u + bi + 1u), qw = (int)(bj * 9u + bi);
-    const int qn = (int)(bi * 9u + bj + 1u), qs = (int)(bi * 9u + bj);
     T FE[3], FW[3], GN[3], GS[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        FE[k] = s.F[0][k][qe];
-        FW[k] = s.F[0][k][qw];
-        GN[k] = s.F[1][k][qn];
-        GS[k] = s.F[1][k][qs];
+        FE[k] = s.F[0][k][kc.qe];
+        FW[k] = s.F[0][k][kc.qw];
+        GN[k] = s.F[1][k][kc.qn];
+        GS[k] = s.F[1][k][kc.qs];
     }
-    const T hcE = s.hl[0][qe], hcW = s.hr[0][qw];
-    const T hcN = s.hl[1][qn], hcS = s.hr[1][qs];
-    const bool inW = (I0 + bi) != 0u;
+    const T hcE = s.hl[0][kc.qe], hcW = s.hr[0][kc.qw];
+    const T hcN = s.hl[1][kc.qn], hcS = s.hr[1][kc.qs];
+    const bool inW = (I0 + kc.bi) != 0u;
     fv1_finish<T>(x, L, c, inW, own, FE, FW, GN, GS, hcE, hcW, hcN, hcS, x.dx, x.dy,
                   (uint64_t)c, 1u, acc);
     // the next block's LDS writes must not overtake this block's reads
@@ -1834,6 +1912,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
     __shared__ double rxy[2 * (HW_MAX_L + 1)];
     __shared__ const uint8_t* wtab[kMaxScen];
     __shared__ BlockLds<T> blds[kBlock / kWave];
+    const BlockConst kc = block_const();
     const int tid = threadIdx.x;
     const int wid = tid / kWave;
     const int lane = tid & (kWave - 1);
@@ -1901,7 +1980,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
                 if (finest && x.L >= 3) {
                     // one aligned 8 x 8 block of finest leaves per wave
                     const uint32_t c0 = base + u * kBlock + w * kWave;
-                    if (c0 < x.nl) fv1_block<T>(x, c0, acc, blds[wid]);
+                    if (c0 < x.nl) fv1_block<T>(x, c0, acc, blds[wid], kc);
                 } else if (leaf < x.nl) {
                     if (finest) fv1_leaf<T, true>(x, fin_off + leaf, acc);
                     else fv1_leaf<T, false>(x, x.leaves[leaf], acc);
