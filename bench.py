@@ -67,8 +67,9 @@ def phase_bytes(L, w, hist, dry=None, uniform=False, sparse=False, fv1_grid=2048
     fill      only when some leaf is coarser than a group: read the fill
               table, write the finest cells of coarser leaves (with the
               tree-sparse set, `sparse`, 64 cells of each 1024-cell span
-              below a leaf of level <= L-5)
-    finalize  read the partial records of both FV1 kernels (80 B each)
+              below a leaf of level <= L-5); and, in the same launch, the
+              finalisation: read the partial records of both FV1 kernels
+              (80 B each)
 
     uniform FV1 plan (FV1 and finalize only): every finest cell reads its
     depth (neighbours cached); the full update reads h, qx, qy and z and
@@ -114,13 +115,14 @@ def phase_bytes(L, w, hist, dry=None, uniform=False, sparse=False, fv1_grid=2048
     if not all_finest:
         traverse += groups + 4 * nl + 4 * groups + N
         fill = 4 * groups + 3 * w * fill_writes
+    # the finalisation runs in the copy-down's launch (its phase time too)
     return {
         "encode": 3 * w * N + 3 * w * (Nc - 4 ** (L - 1)) + 2 * Nc + blocks * (1 + 16),
         "regularise": 2 * Nc,
         "traverse": traverse,
         "fv1": int(fv1),
-        "fill": fill,
-        "finalize": finalize,
+        "fill": fill + finalize,
+        "finalize": 0,
         "n_leaves": nl,
     }
 

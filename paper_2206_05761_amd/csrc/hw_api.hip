@@ -34,7 +34,8 @@ hipError_t launch_export(int prec, const Desc* dd, uint64_t N, double* h,
                          double* qx, double* qy, hipStream_t s);
 hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
                            int waves, hipStream_t s);
-hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, hipStream_t s);
+hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, uint32_t grid,
+                       hipStream_t s);
 hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t s);
 hipError_t launch_forget(const Desc* dd, uint64_t nhist, hipStream_t s);
 hipError_t launch_densify(int prec, const Desc* dd, int L, hipStream_t s);
@@ -356,11 +357,13 @@ hipError_t enqueue_phase(hw_plan* pl, int phase, hipStream_t s)
                                 0, s);
         break;
     case HW_PH_FILL:
+        // the copy-down and the finalisation share one launch
         e = hw::launch_fill(pl->precision, Launch{pl->d_desc, pl->trav_prefix, n},
-                            pl->trav_blocks, s);
+                            pl->trav_blocks, pl->fv1_grid, s);
         break;
     case HW_PH_FINALIZE:
-        e = hw::launch_finalize(pl->d_desc, n, pl->fv1_grid, s);
+        // a uniform FV1 plan has no copy-down: it finalises on its own
+        if (pl->uniform) e = hw::launch_finalize(pl->d_desc, n, pl->fv1_grid, s);
         break;
     }
     return e;

@@ -15,6 +15,10 @@ constexpr int kPartial = 10;            // doubles per FV1 partial record
 constexpr int kMaxScen = 64;            // problems per batch
 constexpr int kMaxFv1Grid = 8192;
 constexpr int kLeafBatch = 2;           // leaves per FV1 thread per iteration
+// Slots of hw_scalars.acc holding the step's snapshot of cur and done,
+// taken by the light FV1 kernel for the copy-down.
+constexpr int STEP_CUR = 4;
+constexpr int STEP_DONE = 5;
 
 // Everything a kernel needs to know about one problem.  Lives in device
 // memory (the workspace for single-problem calls, the plan for batches).

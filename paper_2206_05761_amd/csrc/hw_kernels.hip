@@ -11,17 +11,20 @@
 //                 dry with dry neighbours are finished there ((h, 0, 0)), the
 //                 others marked for the heavy kernel.
 //   k_fv1_heavy   FV1 update of the marked leaves with same-level neighbours
-//                 (Fig. 3); both write back to the finest descendants and
-//                 leave partial reductions.
-//   k_fill        copy-down of leaves coarser than a traversal group.
-//   k_finalize    t += dt, CFL timestep, s_max, mass (minimum reduction of
-//                 Section 2.2.3), flip of the finest buffer set.
+//                 (Fig. 3), an 8 x 8 block of finest leaves per wave when all
+//                 leaves are finest; both write back to the finest
+//                 descendants and leave partial reductions.
+//   k_fill_finalize  copy-down of leaves coarser than a traversal group, and
+//                 in the same launch t += dt, CFL timestep, s_max, mass
+//                 (minimum reduction of Section 2.2.3), flip of the finest
+//                 buffer set (k_finalize alone for uniform FV1 plans).
 //
 // The encoding and the significance test perform, compiled without
 // contraction, the same IEEE operations in the same order as the method's
 // definition (their FP64 results are bit-identical to it).  The FV1 update
-// takes one reciprocal where the definition divides several times by the
-// same quantity, so it differs from it by rounding only.
+// takes one Newton-refined reciprocal where the definition divides several
+// times by the same quantity, a Newton inverse cube root for the friction
+// term, and may fuse multiply-adds, so it differs from it by rounding only.
 #include "hw_device.h"
 
 #include <math.h>
@@ -1182,7 +1185,7 @@ __device__ inline void fv1_finish(const Fv1Ctx<T>& x, int m, uint32_t c, bool in
     }
 
     // write-back: every finest descendant of the leaf in the other set,
-    // except for leaves coarser than a traversal group (k_fill copies
+    // except for leaves coarser than a traversal group (the fill copies
     // those from the first descendant)
     store_run<T>(x.fout[0] + f0, cnt, h);
     store_run<T>(x.fout[1] + f0, cnt, qx);
@@ -1810,6 +1813,13 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
     acc_reset(acc);
     Fv1Ctx<T> x;
     gp<uint8_t> wetb = gp<uint8_t>(nullptr);
+    // The step's snapshot of the set and done flag for the copy-down (which
+    // runs in the same launch as the finalisation that changes them).
+    if (blockIdx.x == 0 && tid < n) {
+        const gp<hw_scalars> sc = glob(descs[tid].scal);
+        sc->acc[STEP_CUR] = (double)sc->cur;
+        sc->acc[STEP_DONE] = (double)sc->done;
+    }
     // The problems whose leaves are all finest, then the others, each kind
     // spread over every workgroup (and so over every XCD) on its own: the
     // two kinds cost very differently per chunk.
@@ -2003,22 +2013,22 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
 // 64 groups with consecutive lanes on consecutive cells (the group data go
 // through the wave's slice of LDS).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fill(Launch lc)
+__device__ inline void fill_block(const Launch& lc, uint32_t vb)
 {
     __shared__ uint32_t s_src[kBlock];
     __shared__ uint64_t s_f0[kBlock];
     __shared__ T s_val[3][kBlock];
     uint32_t lb;
-    const int s = scen_of(lc, blockIdx.x, lb);
+    const int s = scen_of(lc, vb, lb);
     const Desc& d = lc.descs[s];
     const hw_scalars* sc = d.scal;
-    if (sc->done) return;
+    if (sc->acc[STEP_DONE] != 0.0) return;
     if (sc->n_leaves == (1ull << (2 * d.L))) return;   // no coarser leaf at all
     const int L = d.L, Lg = d.group_level;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1u), w0 = tid & ~(kWave - 1u);
     const uint32_t g = lb * kBlock + tid;
-    const int o = uniform((int)sc->cur) ^ 1;
+    const int o = uniform((int)sc->acc[STEP_CUR]) ^ 1;
     gp<T> a[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) a[v] = glob(reinterpret_cast<T*>(d.fine[o][v]));
@@ -2070,12 +2080,9 @@ __global__ __launch_bounds__(kBlock) void k_fill(Launch lc)
 // than its wider reduction saves (1024 threads: 4.5 us more per step).
 constexpr int kFinalBlock = 256;
 
-__global__ __launch_bounds__(kFinalBlock) void k_finalize(const Desc* descs,
-                                                          int fv1_grid)
+__device__ inline void finalize_problem(const Desc& d, int fv1_grid,
+                                        double (*red)[kPartial], double* tot)
 {
-    __shared__ double red[kFinalBlock / kWave][kPartial];
-    __shared__ double tot[kPartial];
-    const Desc& d = descs[blockIdx.x];
     const gp<hw_scalars> sc = glob(d.scal);
     // Every value this kernel reads is requested before any is used: the
     // scalars, and the records (four per thread and round; a record past the
@@ -2149,6 +2156,34 @@ __global__ __launch_bounds__(kFinalBlock) void k_finalize(const Desc* descs,
         sc->cur ^= 1u;
         sc->done = (tn < d.t_end) ? 0u : 1u;
     }
+}
+
+__global__ __launch_bounds__(kFinalBlock) void k_finalize(const Desc* descs, int fv1_grid)
+{
+    __shared__ double red[kFinalBlock / kWave][kPartial];
+    __shared__ double tot[kPartial];
+    finalize_problem(descs[blockIdx.x], fv1_grid, red, tot);
+}
+
+// The copy-down and the finalisation in one launch: the first n workgroups
+// finalise one problem each (dispatched first: the finalisation is the
+// longer chain), the others fill.  The fill reads the finest set and the
+// done flag from the step's snapshot (STEP_CUR, STEP_DONE, taken by the
+// light FV1 kernel), not from cur and done, which the finalising
+// workgroups update in the same launch.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill_finalize(Launch lc, uint32_t fill_blocks,
+                                                          int fv1_grid)
+{
+    static_assert(kFinalBlock == kBlock, "one workgroup size for both parts");
+    __shared__ double red[kFinalBlock / kWave][kPartial];
+    __shared__ double tot[kPartial];
+    const uint32_t nf = (uint32_t)lc.n;
+    if (blockIdx.x < nf) {
+        finalize_problem(lc.descs[blockIdx.x], fv1_grid, red, tot);
+        return;
+    }
+    fill_block<T>(lc, blockIdx.x - nf);
 }
 
 // ---------------------------------------------------------------------------
@@ -2384,12 +2419,18 @@ hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
     return hipGetLastError();
 }
 
-hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, hipStream_t s)
+// Copy-down and finalisation of the step (fill.n problems, FV1 grid grid).
+hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, uint32_t grid,
+                       hipStream_t s)
 {
+    const dim3 blocks(fill_blocks + (uint32_t)fill.n);
+    const int records = (int)(grid + heavy_grid(grid));
     if (prec == HW_FP64)
-        hipLaunchKernelGGL(k_fill<double>, dim3(fill_blocks), dim3(kBlock), 0, s, fill);
+        hipLaunchKernelGGL(k_fill_finalize<double>, blocks, dim3(kBlock), 0, s, fill,
+                           fill_blocks, records);
     else
-        hipLaunchKernelGGL(k_fill<float>, dim3(fill_blocks), dim3(kBlock), 0, s, fill);
+        hipLaunchKernelGGL(k_fill_finalize<float>, blocks, dim3(kBlock), 0, s, fill,
+                           fill_blocks, records);
     return hipGetLastError();
 }
 
@@ -2404,8 +2445,7 @@ hipError_t launch_fv1(int prec, const Desc* descs, int n, uint32_t grid,
                       Launch fill, uint32_t fill_blocks, hipStream_t s)
 {
     hipError_t e = launch_fv1_only(prec, descs, n, grid, 0, s);
-    if (e == hipSuccess) e = launch_fill(prec, fill, fill_blocks, s);
-    if (e == hipSuccess) e = launch_finalize(descs, n, grid, s);
+    if (e == hipSuccess) e = launch_fill(prec, fill, fill_blocks, grid, s);
     return e;
 }
 
