@@ -214,6 +214,21 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     const int n_mid = n_in - cp;                  // level held per thread
     const uint32_t M = 1u << (2 * (lv - cp));     // active threads
 
+    // Paired form of the first FP64 pass (four cells per thread, full
+    // tiles): lane l of wave w loads, per variable, cells (2l, 2l+1) of the
+    // wave's first 128 finest cells and of its second 128 with non-temporal
+    // 16-byte loads, so that each load instruction of the wave covers 1 KB
+    // once; even and odd lanes then swap one pair, and even lane 2j holds
+    // the four children of the wave's level-(n_in-1) cell j, odd lane 2j+1
+    // those of cell 32 + j.  pidx is the thread's level-(n_in-1) cell in the
+    // tile (tid in the other forms).
+    const uint32_t lane = (uint32_t)tid & (kWave - 1u);
+    const uint32_t wid = (uint32_t)tid / kWave;
+    const bool paired = FLOW && sizeof(T) == 8 && pass == 0 && (CP == 1 || cp == 1) &&
+                        M == (uint32_t)kBlock;
+    const uint32_t pidx = paired ? kWave * wid + ((lane & 1u) ? 32u : 0u) + (lane >> 1)
+                                 : (uint32_t)tid;
+
     // The static bed flags of every cell this thread will emit, requested
     // together with the child values (one round trip instead of one per
     // level).  Tail level i is n_mid - 1 - i, with M >> 2(i+1) threads.
@@ -223,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
         if ((uint32_t)tid < M) {
             const uint64_t o1 = level_off(n_in - 1) + ((uint64_t)b << (2 * (lv - 1)));
             if (CP == 1 || cp == 1) {
-                zr[0] = zsig[o1 + tid];
+                zr[0] = zsig[o1 + pidx];
             } else {
 #pragma unroll
                 for (int qq = 0; qq < 4; ++qq) zr[qq] = zsig[o1 + 4ull * tid + qq];
@@ -259,12 +274,12 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     const gp<uint8_t> dryb = glob(d.dryb);
     const gp<double> bpart = glob(d.bpart);
     auto block_test = [&](const double* hs) {
-        const uint64_t first = ((uint64_t)b << (2 * lv)) + (uint64_t)cells * tid;
+        const uint64_t first = ((uint64_t)b << (2 * lv)) + (uint64_t)cells * pidx;
         const uint32_t blk = (uint32_t)(first >> 6);
         const double tolD = (double)tolT;
         // this thread's square inside the block: side sq, corner (ti, tj)
         const int sq = cells == 4 ? 2 : 4;
-        const uint32_t r = (uint32_t)(tid % tpb);
+        const uint32_t r = pidx % (uint32_t)tpb;
         const int ti = (int)compact1by1(r) * sq, tj = (int)compact1by1(r >> 1) * sq;
         bool wet = false, inflow = false, ww = false, we = false, ws = false, wn = false;
         double m = 0.0, hm = 0.0;
@@ -282,21 +297,27 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
             const double a = fabs(hs[q]);
             hm = a > hm ? a : hm;
         }
-        // combine over the block's tpb consecutive lanes (aligned group)
-        const int lane = tid & (kWave - 1);
-        const uint64_t gmask = (tpb == 64 ? ~0ull : ((1ull << tpb) - 1ull)) << (lane & ~(tpb - 1));
+        // combine over the block's tpb lanes: an aligned run of consecutive
+        // lanes, or in the paired form the lanes of one parity in one half
+        // of the wave (stride 2)
+        const int ln = tid & (kWave - 1);
+        const uint64_t gmask =
+            paired ? (((ln & 1) ? 0xAAAAAAAAull : 0x55555555ull) << (ln & 32))
+                   : (tpb == 64 ? ~0ull : ((1ull << tpb) - 1ull)) << (ln & ~(tpb - 1));
         const bool bw = (__ballot(wet) & gmask) != 0ull;
         const bool bi = (__ballot(inflow) & gmask) != 0ull;
         const bool bww = (__ballot(ww) & gmask) != 0ull;
         const bool bwe = (__ballot(we) & gmask) != 0ull;
         const bool bws = (__ballot(ws) & gmask) != 0ull;
         const bool bwn = (__ballot(wn) & gmask) != 0ull;
-        for (int o = 1; o < tpb; o <<= 1) {
+        const int ostep = paired ? 2 : 1;
+        for (int o = ostep; o < ostep * tpb; o <<= 1) {
             m += __shfl_xor(m, o);
             const double y = __shfl_xor(hm, o);
             hm = y > hm ? y : hm;
         }
-        if ((lane & (tpb - 1)) == 0) {
+        const bool leader = paired ? (ln & 30) == 0 : (ln & (tpb - 1)) == 0;
+        if (leader) {
             dryb[blk] = (uint8_t)((bw ? 1 : 0) | (bi ? 2 : 0) | (bww ? 4 : 0) |
                                           (bwe ? 8 : 0) | (bws ? 16 : 0) | (bwn ? 32 : 0));
             gp<double> bp = bpart + 2ull * blk;
@@ -340,10 +361,30 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
                         for (int q = 0; q < 4; ++q) ch[v][q] = (double)src[v][base + q];
                 }
             };
-            if (covered) load_children(wf);
-            else load_children(tile_in + 4ull * tid);
+            if (covered) {
+                load_children(wf);   // the same cells on every lane
+            } else if (paired) {
+                const uint64_t wb = tile_in + 256ull * wid + 2ull * lane;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const gp<const vd2> q = reinterpret_cast<gp<const vd2>>(src[v] + wb);
+                    const vd2 x0 = __builtin_nontemporal_load(q);
+                    const vd2 x1 = __builtin_nontemporal_load(q + 64);
+                    const bool odd = (lane & 1u) != 0u;
+                    const vd2 give = odd ? x0 : x1;
+                    vd2 got;
+                    got.x = __shfl_xor(give.x, 1);
+                    got.y = __shfl_xor(give.y, 1);
+                    ch[v][0] = odd ? got.x : x0.x;
+                    ch[v][1] = odd ? got.y : x0.y;
+                    ch[v][2] = odd ? x1.x : got.x;
+                    ch[v][3] = odd ? x1.y : got.y;
+                }
+            } else {
+                load_children(tile_in + 4ull * tid);
+            }
             if (blocks) block_test(ch[0]);
-            emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + tid, ch, p, zr[0]);
+            emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + pidx, ch, p, zr[0]);
         } else {
             double ch[4][NV][4];
             auto load_children = [&](uint64_t base) {
@@ -388,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     __shared__ double lds[NV][kBlock];
     if ((uint32_t)tid < M) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) lds[v][tid] = p[v];
+        for (int v = 0; v < NV; ++v) lds[v][pidx] = p[v];
     }
     __syncthreads();
     if (tid >= kWave) return;
