@@ -101,7 +101,7 @@ uint32_t encode_blocks(int L, int pass, int tl)
 }
 
 struct WorkLayout {
-    size_t desc, tcount, big_src, gcode, lmap, wet, hist, dryb, bpart, partials, total;
+    size_t desc, tcount, big_src, gcode, lmap, wet, hist, dryb, bpart, partials, rsig, total;
 };
 
 // Entries of the FV1 write history: one per 64-cell Morton block of the
@@ -132,6 +132,9 @@ WorkLayout work_layout(int L)
     o = align_up(o + 2 * n_hist(L) * sizeof(double));
     w.partials = o;
     o = align_up(o + 2 * (size_t)hw::kMaxFv1Grid * hw::kPartial * sizeof(double));
+    // one record per regularisation workgroup
+    w.rsig = o;
+    o = align_up(o + n_reg_blocks(L));
     w.total = o;
     return w;
 }
@@ -249,6 +252,8 @@ Desc make_desc(const hw_problem* p, const hw_buffers* b, double* partials)
     d.bpart = reinterpret_cast<double*>(wk + w.bpart);
     d.nhist = (uint32_t)n_hist(p->L);
     d.partials = partials ? partials : reinterpret_cast<double*>(wk + w.partials);
+    d.rsig = reinterpret_cast<uint8_t*>(wk + w.rsig);
+    d.nreg = n_reg_blocks(p->L);
     d.ntrav = n_trav(p->L);
     return d;
 }
@@ -588,9 +593,8 @@ size_t hw_workspace_bytes(const hw_problem* p)
 void hw_default_tuning(const hw_problem* p, hw_tuning* out)
 {
     if (!out) return;
-    const int L = p && p->L >= 1 && p->L <= HW_MAX_L ? p->L : 10;
-    const bool fp32 = p && p->precision == HW_FP32_BULK;
-    out->encode_cells_per_thread = (fp32 && L >= 10) ? 16 : 4;
+    (void)p;
+    out->encode_cells_per_thread = 4;
     out->fv1_block = hw::kBlock;
     out->fv1_grid = 0;
     out->fv1_write_skip = 1;
@@ -708,6 +712,7 @@ int mra_traverse_leaves_noalloc(const hw_problem* p, const hw_buffers* b,
     d.dryb = nullptr;
     d.bpart = nullptr;
     d.partials = nullptr;
+    d.rsig = nullptr;
     Desc* dd = reinterpret_cast<Desc*>(sb + t.desc);
     hipError_t e = hw::launch_set_desc(d, dd, stream);
     if (e != hipSuccess) return hip_fail(e, "descriptor upload");

@@ -41,6 +41,8 @@ struct Desc {
     uint32_t* big_src;     // per group: leaf index of a coarser leaf or kNone
     uint8_t* lmap;         // per finest cell: level of the leaf containing it
     uint8_t* gcode;        // per traversal group: walk summary (count pass)
+    uint8_t* rsig;         // per regularisation workgroup: every flag it
+                           // wrote this step is set
     uint8_t* wet;          // FV1 wet table: 4 bytes per super-chunk
     uint64_t* hist;        // FV1 write history: one entry per 64 finest cells
     uint8_t* dryb;         // per 64 finest cells: the dry case holds for all
@@ -49,6 +51,7 @@ struct Desc {
     double* partials;      // FV1 / ingest partial records, kPartial each
     uint32_t ntrav;        // traversal workgroups of this problem
     uint32_t nhist;        // entries of hist
+    uint32_t nreg;         // regularisation workgroups (records in rsig)
     int32_t full_outputs;  // write every output (the entry points) or only
                            // what the time loop reads (plans): coarse level
                            // L-1, and the leaf list, leaf-level map and fill

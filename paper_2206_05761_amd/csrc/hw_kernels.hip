@@ -91,6 +91,18 @@ __device__ inline void load4(gp<const float> p, double o[4])
     o[3] = a.w;
 }
 
+// The same with a non-temporal load (data read once per step: a wave of
+// consecutive lanes covers 1 KB per instruction).
+__device__ inline void load4_nt(gp<const float> p, double o[4])
+{
+    const vf4 a = __builtin_nontemporal_load(reinterpret_cast<gp<const vf4>>(p));
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = a.z;
+    o[3] = a.w;
+}
+__device__ inline void load4_nt(gp<const double> p, double o[4]) { load4(p, o); }
+
 // ---------------------------------------------------------------------------
 // Encoding with fused significance flags
 // ---------------------------------------------------------------------------
@@ -380,6 +392,9 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
                     ch[v][2] = odd ? x1.x : got.x;
                     ch[v][3] = odd ? x1.y : got.y;
                 }
+            } else if (FLOW && pass == 0 && sizeof(T) == 4) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) load4_nt(src[v] + tile_in + 4ull * tid, ch[v]);
             } else {
                 load_children(tile_in + 4ull * tid);
             }
@@ -480,26 +495,45 @@ __global__ __launch_bounds__(kBlock) void k_flag_only(Launch lc)
     d.raw[c] = fl ? 1 : 0;
 }
 
-// ---------------------------------------------------------------------------
-// Regularisation: sig = raw of the cell or of any in-domain face neighbour
-// on the same level.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_regularise(Launch lc)
+// A time-loop step (not the entry points) in which every coarse cell is
+// significant after regularisation has every finest cell as a leaf: every
+// walk reaches the finest level, so the traversal's count pass has nothing
+// to add (the emit pass and the FV1 kernels take the case from n_leaves =
+// 4^L).  Each regularisation workgroup records whether every flag it wrote
+// is set (rsig, one byte each); a workgroup of the count pass or the scan
+// reads all the records (a few KB) and decides.  Not when the current set has spans the previous tree left
+// stale: the emit pass then completes them from the count pass's walk
+// codes.  Must be reached by the whole workgroup.
+__device__ inline bool all_significant_step(const Desc& d, uint32_t* lds)
 {
-    uint32_t b;
-    const int s = scen_of(lc, blockIdx.x, b);
-    const Desc& d = lc.descs[s];
-    if (d.scal->done) return;
-    const int L = d.L;
-    const gp<const uint8_t> raw = glob(static_cast<const uint8_t*>(d.raw));
-    const gp<uint8_t> sig = glob(d.sig);
-    // One thread per 2x2 Morton block of cells on levels 1..L-1; block t
-    // of the whole index space [0, (4^(L-1)-1)/3) sits on level
-    // n = level_of(t) + 1 with block code q.  Thread 0 also does level 0,
-    // which has no neighbours.
-    const uint32_t t = b * kBlock + threadIdx.x;
-    if (t == 0) sig[0] = raw[0] ? 1 : 0;
-    if (L < 2 || t >= (uint32_t)level_off(L - 1)) return;
+    const hw_scalars* sc = d.scal;
+    if (d.full_outputs) return false;
+    const bool stale = sparse_fine(d) && sc->step > 0 && sc->map_step == (uint32_t)sc->step;
+    if (stale) return false;
+    if (!d.rsig) return false;
+    // records read as words (the region is 256-byte aligned); the last
+    // word's bytes past nreg are masked off
+    const gp<const uint32_t> r = reinterpret_cast<gp<const uint32_t>>(glob(d.rsig));
+    const uint32_t words = (d.nreg + 3u) / 4u;
+    bool zero = false;
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) {
+        const uint32_t nb = d.nreg - 4u * i;
+        const uint32_t m = nb >= 4u ? 0xffffffffu : (1u << (8u * nb)) - 1u;
+        zero |= (r[i] & m) != (0x01010101u & m);
+    }
+    const bool wz = __ballot(zero) != 0ull;
+    if ((threadIdx.x & (kWave - 1)) == 0) lds[threadIdx.x / kWave] = wz ? 1u : 0u;
+    __syncthreads();
+    uint32_t any = 0;
+    for (uint32_t w = 0; w < blockDim.x / kWave; ++w) any |= lds[w];
+    __syncthreads();
+    return any == 0u;
+}
+
+// The four cells of regularisation block t (levels 1..L-1); returns whether
+// all four are significant.
+__device__ inline bool regularise_block(uint32_t t, gp<const uint8_t> raw, gp<uint8_t> sig)
+{
     const int n = level_of(t) + 1;
     const uint32_t q = t - (uint32_t)level_off(n - 1);
     // blocks live on level n-1: codes use 2(n-1) bits
@@ -530,10 +564,48 @@ __global__ __launch_bounds__(kBlock) void k_regularise(Launch lc)
         n1 = raw[on + 1];
     }
     // children 0 (SW), 1 (SE), 2 (NW), 3 (NE) of the block
-    sig[o] = (r0 | r1 | r2 | w1 | s2) ? 1 : 0;
-    sig[o + 1] = (r1 | r0 | r3 | e0 | s3) ? 1 : 0;
-    sig[o + 2] = (r2 | r3 | r0 | w3 | n0) ? 1 : 0;
-    sig[o + 3] = (r3 | r2 | r1 | e2 | n1) ? 1 : 0;
+    const uint8_t g0 = (r0 | r1 | r2 | w1 | s2) ? 1 : 0;
+    const uint8_t g1 = (r1 | r0 | r3 | e0 | s3) ? 1 : 0;
+    const uint8_t g2 = (r2 | r3 | r0 | w3 | n0) ? 1 : 0;
+    const uint8_t g3 = (r3 | r2 | r1 | e2 | n1) ? 1 : 0;
+    sig[o] = g0;
+    sig[o + 1] = g1;
+    sig[o + 2] = g2;
+    sig[o + 3] = g3;
+    return (g0 & g1 & g2 & g3) != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Regularisation: sig = raw of the cell or of any in-domain face neighbour
+// on the same level.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_regularise(Launch lc)
+{
+    uint32_t b;
+    const int s = scen_of(lc, blockIdx.x, b);
+    const Desc& d = lc.descs[s];
+    if (d.scal->done) return;
+    const int L = d.L;
+    const gp<const uint8_t> raw = glob(static_cast<const uint8_t*>(d.raw));
+    const gp<uint8_t> sig = glob(d.sig);
+    // One thread per 2x2 Morton block of cells on levels 1..L-1; block t
+    // of the whole index space [0, (4^(L-1)-1)/3) sits on level
+    // n = level_of(t) + 1 with block code q.  Thread 0 also does level 0,
+    // which has no neighbours.
+    const uint32_t t = b * kBlock + threadIdx.x;
+    bool zero = false;
+    if (t == 0) {
+        sig[0] = raw[0] ? 1 : 0;
+        zero = raw[0] == 0;
+    }
+    if (L >= 2 && t < (uint32_t)level_off(L - 1)) zero |= !regularise_block(t, raw, sig);
+    // this workgroup's record: every flag it wrote is set
+    const bool wz = __ballot(zero) != 0ull;
+    __shared__ uint32_t vote[kBlock / kWave];
+    if ((threadIdx.x & (kWave - 1)) == 0) vote[threadIdx.x / kWave] = wz ? 1u : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        glob(d.rsig)[b] = (vote[0] | vote[1] | vote[2] | vote[3]) ? 0 : 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -697,6 +769,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     const uint64_t n_leaves = sc->n_leaves, step = sc->step;
     const uint32_t map_step = sc->map_step, cur = sc->cur;
     if (done) return;
+    if (!EMIT && all_significant_step(d, lds)) return;
     // Spans of the current set may be stale when the previous step's tree
     // covered them (the map still describes that tree: it was written in
     // the step that made the set).
@@ -760,6 +833,10 @@ __global__ __launch_bounds__(1024) void k_trav_scan(const Desc* descs)
     __shared__ uint32_t lds[32];
     const Desc& d = descs[blockIdx.x];
     const uint32_t done = glob(d.scal)->done;
+    if (!done && all_significant_step(d, lds)) {
+        if (threadIdx.x == 0) glob(d.scal)->n_leaves = 1ull << (2 * d.L);
+        return;
+    }
     const gp<uint32_t> cnt = glob(d.tcount);
     const uint32_t n = d.ntrav;
     // four consecutive counts per thread and round, loaded together
