@@ -1035,6 +1035,28 @@ __device__ inline double rcp_nr(double x)
 }
 __device__ inline float rcp_nr(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Square root of a finite x >= 0 (the FV1 update's g h and squared
+// speeds): the hardware reciprocal square root estimate y, one coupled
+// Goldschmidt step on g = x y, h = y / 2, then two Newton corrections of g
+// (Markstein's formulation), within about an ulp of the correctly rounded
+// root; x = 0 gives 0 and a NaN stays NaN.  Estimates are taken at
+// max(x, 2^-1000), so a root below 2^-500 is off by less than 2^-500.
+// FP32: the hardware square root (1 ulp).
+__device__ inline double sqrt_nr(double x)
+{
+    const double y = __builtin_amdgcn_rsq(fmax(x, 0x1p-1000));
+    double gq = x * y;
+    double hq = 0.5 * y;
+    const double r = fma(-gq, hq, 0.5);
+    gq = fma(gq, r, gq);
+    hq = fma(hq, r, hq);
+    double d = fma(-gq, gq, x);
+    gq = fma(d, hq, gq);
+    d = fma(-gq, gq, x);
+    return fma(d, hq, gq);
+}
+__device__ inline float sqrt_nr(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // x^(-1/3) for x > 0: a single-precision seed 2^(-log2(x) / 3) from the
 // hardware logarithm and exponential, then Newton steps for y^-3 = x,
 // y += y (1 - x y^3) / 3, each doubling the correct bits (two steps for
@@ -1094,8 +1116,8 @@ __device__ inline void face_flux(T hl, T unl, T utl, double zl, T hr, T unr,
         F[2] = T(0);
         return;
     }
-    const T cl = sqrt(g * hls);
-    const T cr = sqrt(g * hrs);
+    const T cl = sqrt_nr(g * hls);
+    const T cr = sqrt_nr(g * hrs);
     const T ustar = T(0.5) * (unl + unr) + cl - cr;
     const T cstar = T(0.5) * (cl + cr) + T(0.25) * (unl - unr);
     T sl, sr;
@@ -1155,7 +1177,7 @@ __device__ inline double wave_speed(T h, T qx, T qy, T ih, T g, T tol)
     // significance test stay uncontracted)
 #pragma clang fp contract(fast)
     if (!(h > tol)) return 0.0;
-    const T c = sqrt(g * h);
+    const T c = sqrt_nr(g * h);
     const T u = qx * ih;
     const T v = qy * ih;
     const T su = fabs(u) + c;
@@ -1236,19 +1258,19 @@ __device__ inline Cell<T> load_fine(const Fv1Ctx<T>& x, uint32_t k)
     return c;
 }
 
-// The rest of one leaf's FV1 update once its four face fluxes (F: the
-// x-flux (mass, normal, tangential momentum) of the east and west faces, G:
-// the y-flux of the north and south faces) and its own reconstructed depth
-// at each face are known: the Audusse bed-slope terms, forward Euler (Eq. 2)
-// with the level-m cell size, the sources, the write-back to the cnt finest
-// cells from f0 on in the other set, and the partial record.  inW: the leaf
-// has an in-domain west neighbour (no inflow through it).
+// The rest of one leaf's FV1 update once the net fluxes through its four
+// faces are known: mass (e, w, n, s: east, west, north, south faces), the
+// normal momentum flux of each face with the Audusse bed-slope term of the
+// leaf's own side already added (pe, pw, pn, ps), and the tangential
+// momentum flux (te, tw, tn, ts).  Forward Euler (Eq. 2) with the level-m
+// cell size, the sources, the write-back to the cnt finest cells from f0 on
+// in the other set, and the partial record.  inW: the leaf has an
+// in-domain west neighbour (no inflow through it).
 template <typename T>
-__device__ inline void fv1_finish(const Fv1Ctx<T>& x, int m, uint32_t c, bool inW,
-                                  const Cell<T>& own, const T FE[3], const T FW[3],
-                                  const T GN[3], const T GS[3], T hcE, T hcW, T hcN,
-                                  T hcS, double dxm, double dym, uint64_t f0,
-                                  uint32_t cnt, Acc& acc)
+__device__ inline void fv1_update(const Fv1Ctx<T>& x, int m, uint32_t c, bool inW,
+                                  const Cell<T>& own, T me, T mw, T mn, T ms, T pe, T pw,
+                                  T pn, T ps, T te, T tw, T tn, T ts, double dxm, double dym,
+                                  uint64_t f0, uint32_t cnt, Acc& acc)
 {
     // FV1 arithmetic may contract a*b+c into one fused multiply-add (its
     // parity bar is 1e-10, not bit identity; the encoding and the
@@ -1257,19 +1279,11 @@ __device__ inline void fv1_finish(const Fv1Ctx<T>& x, int m, uint32_t c, bool in
     const T g = (T)x.g;
     const T tol = (T)x.h_tol;
     const double dt = x.dt;
-    // Audusse bed-slope term: own-depth pressure minus reconstructed-depth
-    // pressure on each face, added to the normal momentum flux.
-    const T hg = T(0.5) * g;
-    const T h2 = own.h * own.h;
-    const T PE = hg * (h2 - hcE * hcE);
-    const T PW = hg * (h2 - hcW * hcW);
-    const T PN = hg * (h2 - hcN * hcN);
-    const T PS = hg * (h2 - hcS * hcS);
     const T rx = (T)x.rxy[2 * m];
     const T ry = (T)x.rxy[2 * m + 1];
-    T h = own.h - rx * (FE[0] - FW[0]) - ry * (GN[0] - GS[0]);
-    T qx = own.qx - rx * ((FE[1] + PE) - (FW[1] + PW)) - ry * (GN[2] - GS[2]);
-    T qy = own.qy - rx * (FE[2] - FW[2]) - ry * ((GN[1] + PN) - (GS[1] + PS));
+    T h = own.h - rx * (me - mw) - ry * (mn - ms);
+    T qx = own.qx - rx * (pe - pw) - ry * (tn - ts);
+    T qy = own.qy - rx * (te - tw) - ry * (pn - ps);
 
     // sources: rain, west-edge inflow, positivity, dry cells, friction
     if (x.rain_rate != 0.0) h = h + (T)(dt * x.rain_rate);
@@ -1295,7 +1309,7 @@ __device__ inline void fv1_finish(const Fv1Ctx<T>& x, int m, uint32_t c, bool in
         qy = T(0);
     } else if (x.manning_n > 0.0) {
         const T nm = (T)x.manning_n;
-        const T speed = sqrt(qx * qx + qy * qy) * ih;
+        const T speed = sqrt_nr(qx * qx + qy * qy) * ih;
         const T cf = g * nm * nm * inv_cbrt(h);
         const T iden = rcp_nr(T(1) + (T)dt * cf * speed * ih);
         qx = qx * iden;
@@ -1316,6 +1330,32 @@ __device__ inline void fv1_finish(const Fv1Ctx<T>& x, int m, uint32_t c, bool in
     acc.v[4] += ((double)h * dxm) * dym;
     if (!(isfinite((double)h) && isfinite((double)qx) && isfinite((double)qy)))
         acc.v[6] = 1.0;
+}
+
+// Audusse bed-slope term of one side of a face: pressure of the leaf's own
+// depth minus that of its reconstructed depth at the face.
+template <typename T>
+__device__ inline T bed_slope_term(T hg, T h, T hc)
+{
+#pragma clang fp contract(fast)
+    return hg * (h * h - hc * hc);
+}
+
+// fv1_update from the four face fluxes (F: the x-flux (mass, normal,
+// tangential momentum) of the east and west faces, G: the y-flux of the
+// north and south faces) and the leaf's reconstructed depth at each face.
+template <typename T>
+__device__ inline void fv1_finish(const Fv1Ctx<T>& x, int m, uint32_t c, bool inW,
+                                  const Cell<T>& own, const T FE[3], const T FW[3],
+                                  const T GN[3], const T GS[3], T hcE, T hcW, T hcN,
+                                  T hcS, double dxm, double dym, uint64_t f0,
+                                  uint32_t cnt, Acc& acc)
+{
+    const T hg = T(0.5) * (T)x.g;
+    fv1_update<T>(x, m, c, inW, own, FE[0], FW[0], GN[0], GS[0],
+                  FE[1] + bed_slope_term(hg, own.h, hcE), FW[1] + bed_slope_term(hg, own.h, hcW),
+                  GN[1] + bed_slope_term(hg, own.h, hcN), GS[1] + bed_slope_term(hg, own.h, hcS),
+                  FE[2], FW[2], GN[2], GS[2], dxm, dym, f0, cnt, acc);
 }
 
 // The full FV1 update of one leaf (the heavy kernel's path; waves whose
@@ -1390,14 +1430,14 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
 // LDS of one wave's block update: the 8 x 8 cells of the block and their
 // 32 face neighbours on a 10 x 10 local grid (local (i + 1, j + 1) holds
 // block cell (i, j); corners unused), and the 72 x-faces and 72 y-faces
-// touching the block: per face the flux (mass, normal and tangential
-// momentum) and the two reconstructed depths.
+// touching the block: per face the mass flux, the normal momentum flux with
+// the bed-slope term of the left (lower) side added and with that of the
+// right (upper) side added, and the tangential momentum flux.
 template <typename T>
 struct BlockLds {
     T h[100], u[100], v[100];
     double z[100];
-    T F[2][3][72];     // [x, y][component][face]
-    T hl[2][72], hr[2][72];
+    T F[2][4][72];     // [x, y][mass, normal + left term, normal + right term, tangential][face]
 };
 
 // Order LDS writes of the wave before its later LDS reads (the LDS executes
@@ -1472,6 +1512,7 @@ __device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, Bloc
     const int L = x.L;
     const uint32_t lane = threadIdx.x & (kWave - 1u);
     const T g = (T)x.g;
+    const T hg = T(0.5) * g;
     const T tol = (T)x.h_tol;
     const uint32_t side = 1u << L;
     const uint32_t I0 = compact1by1(c0), J0 = compact1by1(c0 >> 1);
@@ -1525,30 +1566,27 @@ __device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, Bloc
         const T unl = isx ? s.u[il] : s.v[il], utl = isx ? s.v[il] : s.u[il];
         const T unr = isx ? s.u[ir] : s.v[ir], utr = isx ? s.v[ir] : s.u[ir];
         T F[3], hls, hrs;
-        face_flux<T>(s.h[il], unl, utl, s.z[il], s.h[ir], unr, utr, s.z[ir], g, tol, F, hls,
-                     hrs);
+        const T hl = s.h[il], hr = s.h[ir];
+        face_flux<T>(hl, unl, utl, s.z[il], hr, unr, utr, s.z[ir], g, tol, F, hls, hrs);
         const int d = isx ? 0 : 1;
         const int qq = kc.fq[p];
         s.F[d][0][qq] = F[0];
-        s.F[d][1][qq] = F[1];
-        s.F[d][2][qq] = F[2];
-        s.hl[d][qq] = hls;
-        s.hr[d][qq] = hrs;
+        s.F[d][1][qq] = F[1] + bed_slope_term(hg, hl, hls);
+        s.F[d][2][qq] = F[1] + bed_slope_term(hg, hr, hrs);
+        s.F[d][3][qq] = F[2];
     }
     wave_lds_sync();
-    T FE[3], FW[3], GN[3], GS[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        FE[k] = s.F[0][k][kc.qe];
-        FW[k] = s.F[0][k][kc.qw];
-        GN[k] = s.F[1][k][kc.qn];
-        GS[k] = s.F[1][k][kc.qs];
-    }
-    const T hcE = s.hl[0][kc.qe], hcW = s.hr[0][kc.qw];
-    const T hcN = s.hl[1][kc.qn], hcS = s.hr[1][kc.qs];
+    // own cell: left of its east and north faces, right of its west and
+    // south faces
+    const T me = s.F[0][0][kc.qe], mw = s.F[0][0][kc.qw];
+    const T mn = s.F[1][0][kc.qn], ms = s.F[1][0][kc.qs];
+    const T pe = s.F[0][1][kc.qe], pw = s.F[0][2][kc.qw];
+    const T pn = s.F[1][1][kc.qn], ps = s.F[1][2][kc.qs];
+    const T te = s.F[0][3][kc.qe], tw = s.F[0][3][kc.qw];
+    const T tn = s.F[1][3][kc.qn], ts = s.F[1][3][kc.qs];
     const bool inW = (I0 + kc.bi) != 0u;
-    fv1_finish<T>(x, L, c, inW, own, FE, FW, GN, GS, hcE, hcW, hcN, hcS, x.dx, x.dy,
-                  (uint64_t)c, 1u, acc);
+    fv1_update<T>(x, L, c, inW, own, me, mw, mn, ms, pe, pw, pn, ps, te, tw, tn, ts, x.dx,
+                  x.dy, (uint64_t)c, 1u, acc);
     // the next block's LDS writes must not overtake this block's reads
     wave_lds_sync();
 }
