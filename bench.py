@@ -38,7 +38,7 @@ def leaf_level_hist(buffers, L):
     return np.bincount(lvl, minlength=L + 1)
 
 
-def phase_bytes(L, w, hist, dry=None, uniform=False, sparse=False, fv1_grid=2048):
+def phase_bytes(L, w, hist, dry=None, uniform=False, sparse=False, fv1_grid=2048, tl=5):
     """Algorithmic HBM bytes of one step per phase (w = bytes per flow word),
     counting only what the step's kernels move.
 
@@ -70,6 +70,13 @@ def phase_bytes(L, w, hist, dry=None, uniform=False, sparse=False, fv1_grid=2048
               below a leaf of level <= L-5); and, in the same launch, the
               finalisation: read the partial records of both FV1 kernels
               (80 B each)
+
+    Two single launches are modelled on their own: encode_first_pass (the
+    first of the encoding passes, levels L-1 .. L-tl: the finest read, the
+    coarse levels it stores, its flags and the 64-cell block records) and
+    fv1_heavy (the full updates: per fully updated leaf of an all-finest
+    step h, qx, qy and z read and h, qx, qy written; in a general step the
+    fv1 figure above less what the light kernel moves, its wet table).
 
     uniform FV1 plan (FV1 and finalize only): every finest cell reads its
     depth (neighbours cached); the full update reads h, qx, qy and z and
@@ -103,13 +110,19 @@ def phase_bytes(L, w, hist, dry=None, uniform=False, sparse=False, fv1_grid=2048
         fv1 = full * (3 * w + 8 + 3 * w) + stored * 4 * w + skipped * w \
             + (N // 64) * 16 + 4 * (N // 512)
         return {"encode": 0, "regularise": 0, "traverse": 0, "fv1": int(fv1), "fill": 0,
-                "finalize": finalize, "n_leaves": N}
+                "finalize": finalize, "n_leaves": N, "encode_first_pass": 0,
+                "fv1_heavy": int(full * (3 * w + 8 + 3 * w))}
     fv1 = nl * (4 + 3 * w + 8) + 3 * w * fv1_writes
+    heavy = fv1 - 4 * (N // 512)
     if dry is not None and all_finest:
         stored, skipped = dry
         full = N - stored - skipped
         fv1 = full * (3 * w + 8 + 3 * w) + stored * 4 * w + blocks * (1 + 8 + 16 + 8) \
             + 4 * (N // 512)
+        heavy = full * (3 * w + 8 + 3 * w)
+    lv = min(L, tl)
+    first = 3 * w * N + 3 * w * sum(4 ** n for n in range(L - lv, L - 1)) \
+        + 2 * sum(4 ** n for n in range(L - lv, L)) + blocks * (1 + 16)
     traverse = Nc + groups + 4 * ntrav
     fill = 0
     if not all_finest:
@@ -124,6 +137,8 @@ def phase_bytes(L, w, hist, dry=None, uniform=False, sparse=False, fv1_grid=2048
         "fill": fill + finalize,
         "finalize": 0,
         "n_leaves": nl,
+        "encode_first_pass": int(first),
+        "fv1_heavy": int(heavy),
     }
 
 
@@ -161,7 +176,8 @@ def time_single(hw, w, precision, steps, warmup, prof_steps, tuning=None, unifor
                leaf_updates=int(s1["leaf_updates"] - s0["leaf_updates"]),
                dry=((s1["dry_stored"] - s0["dry_stored"]) / steps,
                     (s1["dry_skipped"] - s0["dry_skipped"]) / steps),
-               prof={k: v / prof_steps for k, v in prof.items()}, hist=hist,
+               prof={k: prof[k] / prof_steps for k in hw.PHASES},
+               kernel_ms={k: prof[k] / prof_steps for k in hw.PROF_KERNELS}, hist=hist,
                scalars=s2, tuning=best, tuning_table=table, uniform=uniform)
     return res
 
@@ -199,27 +215,63 @@ def load_traffic(name):
     return kv
 
 
+def encode_levels_per_pass(tuning):
+    """Levels per encoding pass of a tuning (one or two levels in registers,
+    plus four in the workgroup's tile)."""
+    return 6 if (tuning or {}).get("encode_cells_per_thread") == 16 else 5
+
+
+# the single launch each phase's roofline is taken on (others: the phase)
+PHASE_KERNEL = {"encode": "encode_first_pass", "fv1": "fv1_heavy"}
+KERNEL_NAMES = {"encode_first_pass": "k_encode (first pass, finest level in)",
+                "fv1_heavy": "k_fv1_heavy"}
+
+
+def main_kernel(dom, phase_ms, kernel_ms):
+    """The single launch the dominant phase's roofline is taken on: its
+    main kernel when that takes at least half of the phase, else the phase
+    (e.g. an FV1 phase of dry steps, where the light kernel dominates)."""
+    k = PHASE_KERNEL.get(dom)
+    if k and kernel_ms.get(k, 0) >= 0.5 * phase_ms[dom]:
+        return k
+    return dom
+
+
 def roofline(res, L, w, precision=None, workload=None, sparse=False):
-    """Dominant phase against the HBM roof (model bytes / HIP-event phase
-    time), its measured traffic when a current counter summary exists, and
-    the whole step: model bytes of every phase over the sum of the phase
+    """The dominant phase's main kernel against the HBM roof: its model bytes
+    over its average launch time (HIP events around that launch alone for
+    the first encoding pass and the heavy FV1 kernel, around the phase
+    otherwise), its measured traffic when a current counter summary exists,
+    and the whole step: model bytes of every phase over the sum of the phase
     times, and measured bytes per step over the same time when a current
     whole-step counter summary exists."""
-    grid = (res.get("tuning") or {}).get("fv1_grid") or 2048
+    tuning = res.get("tuning") or {}
+    grid = tuning.get("fv1_grid") or 2048
     pb = phase_bytes(L, w, res["hist"], res.get("dry"), res.get("uniform", False),
-                     sparse=sparse, fv1_grid=grid)
+                     sparse=sparse, fv1_grid=grid, tl=encode_levels_per_pass(tuning))
     prof = {k: v for k, v in res["prof"].items() if v > 0}
+    kms = res.get("kernel_ms") or {}
     dom = max((k for k in prof), key=lambda k: prof[k])
-    achieved = pb[dom] / (prof[dom] * 1e-3) / 1e9
+    kern = main_kernel(dom, prof, kms)
+    if kern != dom:
+        k_ms, k_bytes, k_name = kms[kern], pb[kern], KERNEL_NAMES[kern]
+    else:
+        k_ms, k_bytes, k_name = prof[dom], pb[dom], dom
+    achieved = k_bytes / (k_ms * 1e-3) / 1e9
     step_ms = sum(prof.values())
     total_bytes = sum(pb[k] for k in prof)
     per_kernel = {k: {"ms": round(prof[k], 5), "model_bytes": int(pb[k]),
                       "GBs": round(pb[k] / (prof[k] * 1e-3) / 1e9, 1) if prof[k] > 0 else None}
                   for k in prof}
+    for k, v in kms.items():
+        if v > 0:
+            per_kernel[k] = {"ms": round(v, 5), "model_bytes": int(pb[k]),
+                             "GBs": round(pb[k] / (v * 1e-3) / 1e9, 1), "within": next(
+                                 p for p, q in PHASE_KERNEL.items() if q == k)}
     traffic = None
     step_measured = None
     if precision and workload:
-        kv = load_traffic(f"traffic_{dom}_{workload}_{precision}")
+        kv = load_traffic(f"traffic_{kern}_{workload}_{precision}")
         if kv:
             traffic = int(float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]))
         kv = load_traffic(f"traffic_step_{workload}_{precision}")
@@ -232,11 +284,11 @@ def roofline(res, L, w, precision=None, workload=None, sparse=False):
                 "source": f"profiles/traffic_step_{workload}_{precision}.txt",
             }
     return {
-        "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+        "bound": "hbm", "kernel": k_name, "phase": dom, "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "algorithmic_bytes": int(pb[dom]),
-        "avg_ms": round(prof[dom], 5),
+        "algorithmic_bytes": int(k_bytes),
+        "avg_ms": round(k_ms, 5),
         "step": {"model_bytes": int(total_bytes), "ms_phases": round(step_ms, 5),
                  "frac": round(total_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                  "measured": step_measured},
@@ -310,12 +362,16 @@ def bench_batch(hw, steps, warmup, n_members):
                (b["dry_skipped"] - a["dry_skipped"]) / 5.0)
         for k, v in phase_bytes(m.L, 4, hist, dry,
                                 sparse=bool(best.get("encode_skip", 1) and best.get("fill_skip", 1)),
-                                fv1_grid=best.get("fv1_grid") or 2048).items():
+                                fv1_grid=best.get("fv1_grid") or 2048,
+                                tl=encode_levels_per_pass(best)).items():
             if k != "n_leaves":
                 pb[k] = pb.get(k, 0) + v
-    pms = {k: v / 5 for k, v in prof.items() if v > 0}
+    pms = {k: prof[k] / 5 for k in hw.PHASES if prof[k] > 0}
+    kms = {k: prof[k] / 5 for k in hw.PROF_KERNELS}
     dom = max(pms, key=lambda k: pms[k])
-    achieved = pb[dom] / (pms[dom] * 1e-3) / 1e9
+    kern = main_kernel(dom, pms, kms)
+    k_ms = kms[kern] if kern != dom else pms[dom]
+    achieved = pb[kern] / (k_ms * 1e-3) / 1e9
     step_ms = sum(pms.values())
     step_bytes = sum(pb[k] for k in pms)
     levels = sorted(m.L for m in members)
@@ -327,10 +383,11 @@ def bench_batch(hw, steps, warmup, n_members):
         "ms_per_step": round(ms / steps, 4), "dtype": "f32 (FP64 significance)",
         "levels": {str(L): levels.count(L) for L in sorted(set(levels))},
         "phase_ms": {k: round(v / 5, 4) for k, v in prof.items()},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES.get(kern, kern), "phase": dom,
+                     "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "algorithmic_bytes": int(pb[dom]), "avg_ms": round(pms[dom], 5),
+                     "algorithmic_bytes": int(pb[kern]), "avg_ms": round(k_ms, 5),
                      "step": {"model_bytes": int(step_bytes), "ms_phases": round(step_ms, 5),
                               "frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
                      "note": "model bytes summed over the members (their leaf levels and "

@@ -397,9 +397,18 @@ int hwfv1_run_batch(hw_plan* plan, int64_t max_steps, hw_stats* stats,
  * Phase timing: run `steps` steps of the plan WITHOUT the graph, launching
  * the same kernels as a replay, with HIP events recorded on `stream` around
  * each phase.  ms_out[HW_NPHASE] receives the total milliseconds per phase
- * (HW_PH_*), summed over the steps.  Synchronises the stream.  For tools
- * that need per-kernel averages (roofline reports).  Like hwfv1_run it
- * ends by completing fine[cur] (not timed).
+ * (HW_PH_*), summed over the steps, and the mean launch time of two single
+ * kernels: ms_out[HW_PROF_ENCODE_FIRST], the first encoding pass (the launch
+ * that reads the finest level), and ms_out[HW_PROF_FV1_HEAVY], the FV1
+ * kernel that performs the full update of wet leaves, each timed over four
+ * extra launches made right after its phase (both write nothing they read,
+ * so the extra launches store the same values; the phase times exclude
+ * them); ms_out must hold HW_NPROF doubles.  Each step is preceded by a
+ * 0.5 ms wait kernel on the stream, so that the host has queued the step's
+ * launches and events before the GPU reaches them (no timed interval
+ * contains host launch latency).  Synchronises the stream.  For tools that need per-kernel averages
+ * (roofline reports).  Like hwfv1_run it ends by completing fine[cur] (not
+ * timed).
  */
 enum {
     HW_PH_ENCODE = 0,     /* all encoding passes (with flags)            */
@@ -408,7 +417,10 @@ enum {
     HW_PH_FV1 = 3,        /* FV1 update and write-back                    */
     HW_PH_FILL = 4,       /* copy-down of coarse leaves                   */
     HW_PH_FINALIZE = 5,   /* reductions, t, dt                            */
-    HW_NPHASE = 6
+    HW_NPHASE = 6,
+    HW_PROF_ENCODE_FIRST = 6,   /* first encoding pass alone (in ENCODE) */
+    HW_PROF_FV1_HEAVY = 7,      /* full-update FV1 kernel alone (in FV1)  */
+    HW_NPROF = 8
 };
 int hw_plan_profile(hw_plan* plan, int64_t steps, double* ms_out,
                     hipStream_t stream);

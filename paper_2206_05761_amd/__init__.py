@@ -359,13 +359,17 @@ class Plan:
 
 
 PHASES = ("encode", "regularise", "traverse", "fv1", "fill", "finalize")
+# single launches inside those phases (HW_PROF_ENCODE_FIRST, HW_PROF_FV1_HEAVY)
+PROF_KERNELS = ("encode_first_pass", "fv1_heavy")
 
 
 def hw_plan_profile(plan, steps, stream=None) -> dict:
-    """Total milliseconds per phase over `steps` un-graphed steps."""
-    out = (C.c_double * len(PHASES))()
+    """Total milliseconds per phase over `steps` un-graphed steps, and of
+    the first encoding pass and the heavy FV1 kernel alone."""
+    keys = PHASES + PROF_KERNELS
+    out = (C.c_double * len(keys))()
     _check(lib().hw_plan_profile(plan.handle, int(steps), out, _stream(stream)))
-    return dict(zip(PHASES, list(out)))
+    return dict(zip(keys, list(out)))
 
 
 def hwfv1_run_batch(plan, max_steps, stats=True, stream=None):

@@ -32,13 +32,30 @@ hipError_t launch_fv1(int prec, const Desc* descs, int n, uint32_t grid,
                       Launch fill, uint32_t fill_blocks, hipStream_t s);
 hipError_t launch_export(int prec, const Desc* dd, uint64_t N, double* h,
                          double* qx, double* qy, hipStream_t s);
-hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
-                           int waves, hipStream_t s);
+hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid, hipStream_t s);
+hipError_t launch_fv1_heavy(int prec, const Desc* descs, int n, uint32_t grid, hipStream_t s);
 hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, uint32_t grid,
                        hipStream_t s);
 hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t s);
 hipError_t launch_forget(const Desc* dd, uint64_t nhist, hipStream_t s);
 hipError_t launch_densify(int prec, const Desc* dd, int L, hipStream_t s);
+// One thread waits until `ticks` of the constant-rate wall clock have
+// passed (at most `ticks` plus one sleep interval; no memory is touched).
+// Used by the phase timing only: while it runs, the host queues the step's
+// launches and events, so no timed interval contains host launch latency.
+__global__ void k_hold(uint64_t ticks)
+{
+    if (threadIdx.x != 0) return;
+    const uint64_t t0 = (uint64_t)wall_clock64();
+    while ((uint64_t)wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(16);
+}
+
+hipError_t launch_hold(uint64_t ticks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hold, dim3(1), dim3(kWave), 0, s, ticks);
+    return hipGetLastError();
+}
+
 }  // namespace hw
 
 using hw::Desc;
@@ -358,8 +375,7 @@ hipError_t enqueue_phase(hw_plan* pl, int phase, hipStream_t s)
         e = hw::launch_traverse(Launch{pl->d_desc, pl->trav_prefix, n}, pl->trav_blocks, s);
         break;
     case HW_PH_FV1:
-        e = hw::launch_fv1_only(pl->precision, pl->d_desc, n, pl->fv1_grid,
-                                0, s);
+        e = hw::launch_fv1_only(pl->precision, pl->d_desc, n, pl->fv1_grid, s);
         break;
     case HW_PH_FILL:
         // the copy-down and the finalisation share one launch
@@ -1003,35 +1019,78 @@ int hw_plan_profile(hw_plan* plan, int64_t steps, double* ms_out, hipStream_t st
     if (!plan) return fail(HW_EINVAL, "plan is NULL");
     if (!ms_out) return fail(HW_EINVAL, "ms_out is NULL");
     if (steps < 0) return fail(HW_EINVAL, "steps must be >= 0");
-    for (int ph = 0; ph < HW_NPHASE; ++ph) ms_out[ph] = 0.0;
-    hipEvent_t ev[HW_NPHASE + 1];
-    for (int k = 0; k <= HW_NPHASE; ++k) {
+    for (int ph = 0; ph < HW_NPROF; ++ph) ms_out[ph] = 0.0;
+    // Per phase a start and an end event; per single-launch figure a start
+    // and an end event around kRepeat more launches of that kernel, made
+    // after its phase (before the next phase starts) on the state its first
+    // launch saw: the first encoding pass and the heavy FV1 kernel write
+    // nothing they read, so the repeats store the same values again.  Their
+    // mean leaves out the dispatch gap that an event next to a single
+    // launch would add.
+    constexpr int kRepeat = 4;
+    constexpr int kEv = 2 * HW_NPHASE + 4;
+    hipEvent_t ev[kEv];
+    for (int k = 0; k < kEv; ++k) {
         hipError_t e = hipEventCreate(&ev[k]);
         if (e != hipSuccess) {
             for (int q = 0; q < k; ++q) (void)hipEventDestroy(ev[q]);
             return hip_fail(e, "event create");
         }
     }
+    hipEvent_t* kev = &ev[2 * HW_NPHASE];
+    const bool enc_first = !plan->uniform && plan->passes > 0 && plan->enc_blocks[0] > 0;
+    // each step is preceded by a 0.5 ms hold on the stream (see launch_hold)
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        khz <= 0)
+        khz = 100000;
+    const uint64_t hold_ticks = (uint64_t)khz / 2;
     int rc = HW_OK;
     for (int64_t st = 0; st < steps && rc == HW_OK; ++st) {
-        hipError_t e = hipEventRecord(ev[0], stream);
+        hipError_t e = hw::launch_hold(hold_ticks, stream);
         for (int ph = 0; ph < HW_NPHASE && e == hipSuccess; ++ph) {
-            e = enqueue_phase(plan, ph, stream);
-            if (e == hipSuccess) e = hipEventRecord(ev[ph + 1], stream);
+            e = hipEventRecord(ev[2 * ph], stream);
+            if (e == hipSuccess) e = enqueue_phase(plan, ph, stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * ph + 1], stream);
+            if (e == hipSuccess && ph == HW_PH_ENCODE && enc_first) {
+                e = hipEventRecord(kev[0], stream);
+                for (int r = 0; r < kRepeat && e == hipSuccess; ++r)
+                    e = hw::launch_encode_flow(plan->precision,
+                                               Launch{plan->d_desc, plan->enc_prefix[0], plan->n},
+                                               plan->enc_blocks[0], 0, plan->tl, plan->cp,
+                                               plan->encode_skip != 0, nullptr, stream);
+                if (e == hipSuccess) e = hipEventRecord(kev[1], stream);
+            }
+            if (e == hipSuccess && ph == HW_PH_FV1) {
+                e = hipEventRecord(kev[2], stream);
+                for (int r = 0; r < kRepeat && e == hipSuccess; ++r)
+                    e = hw::launch_fv1_heavy(plan->precision, plan->d_desc, plan->n,
+                                             plan->fv1_grid, stream);
+                if (e == hipSuccess) e = hipEventRecord(kev[3], stream);
+            }
         }
-        if (e == hipSuccess) e = hipEventSynchronize(ev[HW_NPHASE]);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2 * HW_NPHASE - 1]);
         for (int ph = 0; ph < HW_NPHASE && e == hipSuccess; ++ph) {
             float ms = 0.f;
-            e = hipEventElapsedTime(&ms, ev[ph], ev[ph + 1]);
+            e = hipEventElapsedTime(&ms, ev[2 * ph], ev[2 * ph + 1]);
             ms_out[ph] += ms;
         }
+        float ms = 0.f;
+        if (e == hipSuccess && enc_first) {
+            e = hipEventElapsedTime(&ms, kev[0], kev[1]);
+            ms_out[HW_PROF_ENCODE_FIRST] += ms / kRepeat;
+        }
+        ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, kev[2], kev[3]);
+        ms_out[HW_PROF_FV1_HEAVY] += ms / kRepeat;
         if (e != hipSuccess) rc = hip_fail(e, "phase timing");
     }
     if (rc == HW_OK) {
         hipError_t e = plan_densify(plan, stream);
         if (e != hipSuccess) rc = hip_fail(e, "densify launch");
     }
-    for (int k = 0; k <= HW_NPHASE; ++k) (void)hipEventDestroy(ev[k]);
+    for (int k = 0; k < kEv; ++k) (void)hipEventDestroy(ev[k]);
     return rc ? rc : ok();
 }
 

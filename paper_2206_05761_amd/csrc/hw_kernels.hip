@@ -1102,12 +1102,12 @@ __device__ inline void face_flux(T hl, T unl, T utl, double zl, T hr, T unr,
     // parity bar is 1e-10, not bit identity; the encoding and the
     // significance test stay uncontracted)
 #pragma clang fp contract(fast)
+    // (fmax / fmin: maximum and minimum that return the other operand when
+    // one is NaN, so a NaN depth clips to 0 as the comparison form does)
     const T dzl = (T)(zr - zl);
     const T dzr = (T)(zl - zr);
-    T hls = hl - (dzl > T(0) ? dzl : T(0));
-    T hrs = hr - (dzr > T(0) ? dzr : T(0));
-    if (!(hls > T(0))) hls = T(0);
-    if (!(hrs > T(0))) hrs = T(0);
+    const T hls = fmax(hl - fmax(dzl, T(0)), T(0));
+    const T hrs = fmax(hr - fmax(dzr, T(0)), T(0));
     hls_out = hls;
     hrs_out = hrs;
     if (hls <= tol && hrs <= tol) {
@@ -1120,21 +1120,8 @@ __device__ inline void face_flux(T hl, T unl, T utl, double zl, T hr, T unr,
     const T cr = sqrt_nr(g * hrs);
     const T ustar = T(0.5) * (unl + unr) + cl - cr;
     const T cstar = T(0.5) * (cl + cr) + T(0.25) * (unl - unr);
-    T sl, sr;
-    if (hls <= tol) {
-        sl = unr - T(2) * cr;
-    } else {
-        const T a = unl - cl;
-        const T b = ustar - cstar;
-        sl = a < b ? a : b;
-    }
-    if (hrs <= tol) {
-        sr = unl + T(2) * cl;
-    } else {
-        const T a = unr + cr;
-        const T b = ustar + cstar;
-        sr = a > b ? a : b;
-    }
+    const T sl = hls <= tol ? unr - T(2) * cr : fmin(unl - cl, ustar - cstar);
+    const T sr = hrs <= tol ? unl + T(2) * cl : fmax(unr + cr, ustar + cstar);
     const T ql = hls * unl;
     const T qr = hrs * unr;
     const T Ul[3] = {hls, ql, hls * utl};
@@ -2560,19 +2547,27 @@ uint32_t heavy_grid(uint32_t grid)
     return grid < kHeavy ? grid : kHeavy;
 }
 
-hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid,
-                           int waves, hipStream_t s)
+// The heavy FV1 kernel alone (after the light kernel of the same step: it
+// reads the wet table and writes only the other set and its own records).
+hipError_t launch_fv1_heavy(int prec, const Desc* descs, int n, uint32_t grid, hipStream_t s)
 {
-    (void)waves;
     const uint32_t gh = heavy_grid(grid);
-    if (prec == HW_FP64) {
-        hipLaunchKernelGGL(k_fv1_light<double>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+    if (prec == HW_FP64)
         hipLaunchKernelGGL(k_fv1_heavy<double>, dim3(gh), dim3(kBlock), 0, s, descs, n, grid);
-    } else {
-        hipLaunchKernelGGL(k_fv1_light<float>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+    else
         hipLaunchKernelGGL(k_fv1_heavy<float>, dim3(gh), dim3(kBlock), 0, s, descs, n, grid);
-    }
     return hipGetLastError();
+}
+
+// The light and the heavy FV1 kernels.
+hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid, hipStream_t s)
+{
+    if (prec == HW_FP64)
+        hipLaunchKernelGGL(k_fv1_light<double>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+    else
+        hipLaunchKernelGGL(k_fv1_light<float>, dim3(grid), dim3(kBlock), 0, s, descs, n);
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_fv1_heavy(prec, descs, n, grid, s);
 }
 
 // Copy-down and finalisation of the step (fill.n problems, FV1 grid grid).
@@ -2600,7 +2595,7 @@ hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t 
 hipError_t launch_fv1(int prec, const Desc* descs, int n, uint32_t grid,
                       Launch fill, uint32_t fill_blocks, hipStream_t s)
 {
-    hipError_t e = launch_fv1_only(prec, descs, n, grid, 0, s);
+    hipError_t e = launch_fv1_only(prec, descs, n, grid, s);
     if (e == hipSuccess) e = launch_fill(prec, fill, fill_blocks, grid, s);
     return e;
 }
