@@ -1414,18 +1414,29 @@ __device__ inline void fv1_leaf(const Fv1Ctx<T>& x, uint32_t idx, Acc& acc)
                   (uint64_t)c << sh, m >= x.Lg ? (1u << sh) : 1u, acc);
 }
 
-// LDS of one wave's block update: the 8 x 8 cells of the block and their
-// 32 face neighbours on a 10 x 10 local grid (local (i + 1, j + 1) holds
-// block cell (i, j); corners unused), and the 72 x-faces and 72 y-faces
-// touching the block: per face the mass flux, the normal momentum flux with
-// the bed-slope term of the left (lower) side added and with that of the
-// right (upper) side added, and the tangential momentum flux.
+// LDS of one wave's block update.  Cells: the 8 x 8 cells of the block and
+// their 32 face neighbours on a 10 x 10 local grid (local (i + 1, j + 1)
+// holds block cell (i, j); corners unused), local (i, j) stored at
+// cell_slot(i, j).  Faces, per direction: slot k < 64 holds the west
+// (x) or south (y) face of the block cell in Morton position k, slots 64 + r
+// the east face of row r (x) or the north face of column r (y); per face the
+// mass flux, the normal momentum flux with the bed-slope term of the left
+// (lower) side added and with that of the right (upper) side added, and the
+// tangential momentum flux.
 template <typename T>
 struct BlockLds {
-    T h[100], u[100], v[100];
-    double z[100];
-    T F[2][4][72];     // [x, y][mass, normal + left term, normal + right term, tangential][face]
+    T h[160], u[160], v[160];
+    double z[160];
+    T F[2][4][72];     // [x, y][mass, normal + left term, normal + right term, tangential][slot]
 };
+
+// Slot of local cell (i, j): rows of 16 words, each row rotated by 4 j, so
+// that the cells of any aligned 4 x 4 (and 8 x 4) group of lanes fall in
+// different LDS banks.
+__device__ inline int cell_slot(uint32_t i, uint32_t j)
+{
+    return (int)(16u * j + ((i + 4u * j) & 15u));
+}
 
 // Order LDS writes of the wave before its later LDS reads (the LDS executes
 // one wave's operations in order; this keeps the compiler from moving them).
@@ -1437,16 +1448,18 @@ __device__ inline void wave_lds_sync()
 }
 
 // Per-lane constants of the block update (the same for every block): the
-// lane's cell in the block, its local-grid index and own faces, the faces
-// it computes (pass p: face lane + 64 p, p = 0..2, as below), and its halo
-// cell (lanes 0-31: side lane / 8, position lane % 8).
+// lane's cell in the block, its local slot, the cells on either side of its
+// west and south faces, its boundary face in the third pass (lanes 0-15: the
+// east face of row lane, or the north face of column lane - 8), the slots of
+// its east and north faces, and its halo cell (lanes 0-31: side lane / 8,
+// position lane % 8).
 struct BlockConst {
     uint32_t bi, bj;       // own cell in the block
-    int me;                // own cell on the local grid
-    int fl[3];             // left cell of the lane's face in each pass
-    int fq[3];             // that face's index within its direction
-    int qe, qw, qn, qs;    // own east / west x-faces, north / south y-faces
-    int hidx;              // halo cell on the local grid
+    int me;                // own cell's slot
+    int wl, sl;            // slots of the cells west and south of it
+    int bl, br;            // third pass: slots left and right of the face
+    int qe, qn;            // face slots of the own cell's east and north faces
+    int hidx;              // halo cell's slot
     uint32_t ei, ej;       // block cell next to the halo cell
     int di, dj;            // offset from that block cell to the halo cell
 };
@@ -1457,41 +1470,50 @@ __device__ inline BlockConst block_const()
     const uint32_t lane = threadIdx.x & (kWave - 1u);
     k.bi = compact1by1(lane);
     k.bj = compact1by1(lane >> 1);
-    k.me = (int)(k.bi + 1 + 10 * (k.bj + 1));
-    // face q < 72: x-face between local (b, a) and (b + 1, a), else the
-    // y-face between (a, b) and (a, b + 1), with a = 1 + q' / 9 and
-    // b = q' % 9 for q' = q mod 72
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        const uint32_t q = lane + 64u * (uint32_t)p;
-        const bool isx = q < 72u;
-        const uint32_t qq = isx ? q : q - 72u;
-        const int a = (int)(qq / 9u) + 1, b = (int)(qq % 9u);
-        k.fl[p] = isx ? b + 10 * a : a + 10 * b;
-        k.fq[p] = (int)qq;
-    }
-    k.qe = (int)(k.bj * 9u + k.bi + 1u);
-    k.qw = (int)(k.bj * 9u + k.bi);
-    k.qn = (int)(k.bi * 9u + k.bj + 1u);
-    k.qs = (int)(k.bi * 9u + k.bj);
-    const uint32_t h = lane & 7u;
+    k.me = cell_slot(k.bi + 1, k.bj + 1);
+    k.wl = cell_slot(k.bi, k.bj + 1);
+    k.sl = cell_slot(k.bi + 1, k.bj);
+    const uint32_t r = lane & 7u;
+    k.bl = lane < 8u ? cell_slot(8, r + 1) : cell_slot(r + 1, 8);
+    k.br = lane < 8u ? cell_slot(9, r + 1) : cell_slot(r + 1, 9);
+    k.qe = k.bi < 7u ? (int)morton(k.bi + 1, k.bj) : 64 + (int)k.bj;
+    k.qn = k.bj < 7u ? (int)morton(k.bi, k.bj + 1) : 64 + (int)k.bi;
     const uint32_t dir = (lane >> 3) & 3u;   // HW_W, HW_E, HW_S, HW_N
     const bool xdir = dir < 2u;
-    k.ei = xdir ? (dir == (uint32_t)HW_W ? 0u : 7u) : h;
-    k.ej = xdir ? h : (dir == (uint32_t)HW_S ? 0u : 7u);
+    k.ei = xdir ? (dir == (uint32_t)HW_W ? 0u : 7u) : r;
+    k.ej = xdir ? r : (dir == (uint32_t)HW_S ? 0u : 7u);
     k.di = dir == (uint32_t)HW_W ? -1 : dir == (uint32_t)HW_E ? 1 : 0;
     k.dj = dir == (uint32_t)HW_S ? -1 : dir == (uint32_t)HW_N ? 1 : 0;
-    k.hidx = xdir ? (dir == (uint32_t)HW_W ? 0 : 9) + 10 * (int)(h + 1)
-                  : (int)(h + 1) + (dir == (uint32_t)HW_S ? 0 : 90);
+    k.hidx = xdir ? cell_slot(dir == (uint32_t)HW_W ? 0u : 9u, r + 1)
+                  : cell_slot(r + 1, dir == (uint32_t)HW_S ? 0u : 9u);
     return k;
+}
+
+// One face of the block update from the staged cells (left / right slots il,
+// ir; x: normal velocity u, y: v), stored in face slot q of direction d.
+template <typename T>
+__device__ inline void block_face(BlockLds<T>& s, int il, int ir, bool isx, int d, int q,
+                                  T g, T hg, T tol)
+{
+    const T hl = s.h[il], hr = s.h[ir];
+    const T ul = s.u[il], vl = s.v[il], ur = s.u[ir], vr = s.v[ir];
+    T F[3], hls, hrs;
+    face_flux<T>(hl, isx ? ul : vl, isx ? vl : ul, s.z[il], hr, isx ? ur : vr, isx ? vr : ur,
+                 s.z[ir], g, tol, F, hls, hrs);
+    s.F[d][0][q] = F[0];
+    s.F[d][1][q] = F[1] + bed_slope_term(hg, hl, hls);
+    s.F[d][2][q] = F[1] + bed_slope_term(hg, hr, hrs);
+    s.F[d][3][q] = F[2];
 }
 
 // The full FV1 update of the 64 finest leaves of one aligned 8 x 8 Morton
 // block (cells c0 .. c0 + 63 of a problem whose leaves are all finest,
 // L >= 3), by one wave.  The result is fv1_leaf's for each cell: every face
 // flux is the same call with the same arguments, made once per face instead
-// of once from each side (144 faces for 64 cells instead of 256), and each
-// cell's velocities are formed once instead of once per face that uses them.
+// of once from each side (144 faces for 64 cells instead of 256: each lane's
+// west face, each lane's south face, then the 16 faces on the block's east
+// and north edges), and each cell's velocities are formed once instead of
+// once per face that uses them.
 template <typename T>
 __device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, BlockLds<T>& s,
                                  const BlockConst& kc)
@@ -1542,35 +1564,22 @@ __device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, Bloc
         s.z[kc.hidx] = hc.z;
     }
     wave_lds_sync();
-    // faces: pass 0 x-faces 0..63; pass 1 x-faces 64..71 (lanes 0-7) and
-    // y-faces 0..55; pass 2 y-faces 56..71 (lanes 0-15)
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        if (p == 2 && lane >= 16u) break;
-        const bool isx = p == 0 || (p == 1 && lane < 8u);
-        const int il = kc.fl[p];
-        const int ir = isx ? il + 1 : il + 10;
-        const T unl = isx ? s.u[il] : s.v[il], utl = isx ? s.v[il] : s.u[il];
-        const T unr = isx ? s.u[ir] : s.v[ir], utr = isx ? s.v[ir] : s.u[ir];
-        T F[3], hls, hrs;
-        const T hl = s.h[il], hr = s.h[ir];
-        face_flux<T>(hl, unl, utl, s.z[il], hr, unr, utr, s.z[ir], g, tol, F, hls, hrs);
-        const int d = isx ? 0 : 1;
-        const int qq = kc.fq[p];
-        s.F[d][0][qq] = F[0];
-        s.F[d][1][qq] = F[1] + bed_slope_term(hg, hl, hls);
-        s.F[d][2][qq] = F[1] + bed_slope_term(hg, hr, hrs);
-        s.F[d][3][qq] = F[2];
+    block_face<T>(s, kc.wl, kc.me, true, 0, (int)lane, g, hg, tol);
+    block_face<T>(s, kc.sl, kc.me, false, 1, (int)lane, g, hg, tol);
+    if (lane < 16u) {
+        const bool isx = lane < 8u;
+        block_face<T>(s, kc.bl, kc.br, isx, isx ? 0 : 1, 64 + (int)(lane & 7u), g, hg, tol);
     }
     wave_lds_sync();
     // own cell: left of its east and north faces, right of its west and
     // south faces
-    const T me = s.F[0][0][kc.qe], mw = s.F[0][0][kc.qw];
-    const T mn = s.F[1][0][kc.qn], ms = s.F[1][0][kc.qs];
-    const T pe = s.F[0][1][kc.qe], pw = s.F[0][2][kc.qw];
-    const T pn = s.F[1][1][kc.qn], ps = s.F[1][2][kc.qs];
-    const T te = s.F[0][3][kc.qe], tw = s.F[0][3][kc.qw];
-    const T tn = s.F[1][3][kc.qn], ts = s.F[1][3][kc.qs];
+    const int q = (int)lane;
+    const T me = s.F[0][0][kc.qe], mw = s.F[0][0][q];
+    const T mn = s.F[1][0][kc.qn], ms = s.F[1][0][q];
+    const T pe = s.F[0][1][kc.qe], pw = s.F[0][2][q];
+    const T pn = s.F[1][1][kc.qn], ps = s.F[1][2][q];
+    const T te = s.F[0][3][kc.qe], tw = s.F[0][3][q];
+    const T tn = s.F[1][3][kc.qn], ts = s.F[1][3][q];
     const bool inW = (I0 + kc.bi) != 0u;
     fv1_update<T>(x, L, c, inW, own, me, mw, mn, ms, pe, pw, pn, ps, te, tw, tn, ts, x.dx,
                   x.dy, (uint64_t)c, 1u, acc);
