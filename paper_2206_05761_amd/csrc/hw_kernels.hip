@@ -1631,6 +1631,36 @@ __device__ inline void light_indices(const Fv1Ctx<T>& x, uint32_t base, uint32_t
     }
 }
 
+// Sub-chunks of one super-chunk of a mixed problem that are wet by their
+// leaves' own depths alone: bit u is set when some leaf of sub-chunk u has
+// a depth above h_tol (it fails the dry test whatever its neighbours hold).
+// Returns true when that settles every sub-chunk (each has such a leaf or
+// no leaf at all), so that neither neighbours nor history need be read; a
+// history entry left unrefreshed names an older step and permits no skip.
+// Without rain only (rain makes every sub-chunk wet on the general path).
+template <typename T>
+__device__ inline bool light_wet_by_own_depth(const Fv1Ctx<T>& x, uint32_t base,
+                                              const uint32_t idx[kLeafBatch], uint32_t& bits)
+{
+    const T tol = (T)x.h_tol;
+    T h[kLeafBatch];
+#pragma unroll
+    for (int u = 0; u < kLeafBatch; ++u) {
+        const int m = level_of(idx[u]);
+        h[u] = load_h<T>(x, m, idx[u] - (uint32_t)level_off(m));
+    }
+    bool settled = true;
+    bits = 0;
+#pragma unroll
+    for (int u = 0; u < kLeafBatch; ++u) {
+        const bool ok = base + (uint32_t)u * kBlock + threadIdx.x < x.nl;
+        const bool wet = wave_any(ok && h[u] > tol);
+        if (wet) bits |= 1u << u;
+        else if (wave_any(ok)) settled = false;
+    }
+    return settled;
+}
+
 // Same-level neighbour codes of cell c on level m (the cell itself beyond
 // the domain edge), in the order W, E, S, N.
 __device__ inline void neighbour_codes(uint32_t c, int m, uint32_t nb[4])
@@ -2033,6 +2063,10 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
             } else {
                 uint32_t idx[U];
                 light_indices<T>(x, base, idx);
+                if (x.rain_rate == 0.0 && light_wet_by_own_depth<T>(x, base, idx, bits)) {
+                    if ((tid & (kWave - 1)) == 0) wetb[4ull * sc + wid] = (uint8_t)bits;
+                    continue;
+                }
                 light_probe<T>(x, idx, b);
     #pragma unroll
                 for (int u = 0; u < U; ++u) {

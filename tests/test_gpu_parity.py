@@ -394,3 +394,31 @@ def test_autotune_restores_state_and_picks_a_candidate(hw):
     for x, y in zip(before[:3], after[:3]):
         assert np.array_equal(x, y)
     assert before[3:] == after[3:]
+
+
+@pytest.mark.parametrize("precision", ["fp32_bulk", "fp64"])
+def test_64_member_ensemble_equals_individual_runs(hw, precision):
+    """The benchmark's ensemble shape at smaller levels: 64 members (the
+    plan maximum) with their own L, eps, relief, friction and forcing
+    (dam breaks with open edges, hydrographs through a west inlet), one
+    launch per phase; every member's fields, leaf list, t and step count
+    equal its own single run bit for bit."""
+    ws = W.ensemble_64(n=64, n_steps=15, levels=(4, 5, 6, 7))
+    steps = 15
+    sims = [_sim(hw, w, precision) for w in ws]
+    plan = hw.Plan([s.problem for s in sims], [s.buffers for s in sims])
+    stats = hw.hwfv1_run_batch(plan, steps)
+    log(f"  ensemble of {len(ws)} ({precision}): levels",
+        sorted({w.L for w in ws}), "steps", [st["steps"] for st in stats][:8], "...")
+    for w, s, st in zip(ws, sims, stats):
+        ref = _sim(hw, w, precision)
+        ref.run(steps)
+        assert st["steps"] == ref.scalars()["step"], w.name
+        for x, y in zip(s.export(), ref.export()):
+            assert np.array_equal(x, y), w.name
+        assert np.array_equal(s.buffers.leaf_list(), ref.buffers.leaf_list()), w.name
+        assert s.scalars()["t"] == ref.scalars()["t"], w.name
+        ref.close()
+    plan.close()
+    for s in sims:
+        s.close()
