@@ -2266,8 +2266,10 @@ __device__ inline void fill_block(const Launch& lc, uint32_t vb)
 // than its wider reduction saves (1024 threads: 4.5 us more per step).
 constexpr int kFinalBlock = 256;
 
-__device__ inline void finalize_problem(const Desc& d, int fv1_grid,
-                                        double (*red)[kPartial], double* tot)
+// (always inlined: called from two kernels, it would otherwise become a
+// call, and the call's register convention sets the copy-down's occupancy)
+__device__ __attribute__((always_inline)) inline void finalize_problem(
+    const Desc& d, int fv1_grid, double (*red)[kPartial], double* tot)
 {
     const gp<hw_scalars> sc = glob(d.scal);
     // Every value this kernel reads is requested before any is used: the
