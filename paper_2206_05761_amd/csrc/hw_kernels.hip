@@ -348,6 +348,41 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     // instead of all its cells.
     const bool span_skip = SKIP && FLOW && pass == 0 && d.encode_skip && lv - cp >= 3 && step > 0 &&
                            map_step == (uint32_t)step && n_leaves < (1ull << (2 * L));
+    // A whole tile inside one leaf (of level <= n_lo): every cell of every
+    // level holds the leaf's value and every detail is 0, so each coarse
+    // value is that value and each raw flag the static bed flag.  The
+    // workgroup stores them (and its block records, from the same test)
+    // without the Haar sums, the LDS meet or the first wave's tail.
+    if (SKIP && (CP == 1 || cp == 1) && span_skip && M == (uint32_t)kBlock) {
+        const uint64_t tile_in = (uint64_t)b << (2 * lv);
+        const bool tile_covered =
+            uniform((int)glob(static_cast<const uint8_t*>(d.lmap))[tile_in]) <= n_lo;
+        if (tile_covered) {
+            T val[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) val[v] = src[v][tile_in];
+            if (blocks) {
+                const double hv[4] = {(double)val[0], (double)val[0], (double)val[0],
+                                      (double)val[0]};
+                block_test(hv);
+            }
+            flags[level_off(n_in - 1) + ((uint64_t)b << (2 * (lv - 1))) + pidx] = zr[0] ? 1 : 0;
+            uint32_t cnt = M;
+#pragma unroll
+            for (int i = 0; i < kTail; ++i) {
+                const int n = n_mid - 1 - i;
+                if (n < n_lo) break;
+                cnt >>= 2;
+                if ((uint32_t)tid < cnt) {
+                    const uint64_t k = (uint64_t)b * cnt + tid;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) dst_of(v, n)[k] = val[v];
+                    flags[level_off(n) + k] = zt[i] ? 1 : 0;
+                }
+            }
+            return;
+        }
+    }
     double p[NV];
     if ((uint32_t)tid < M) {
         const uint64_t tile_in = (uint64_t)b << (2 * lv);
