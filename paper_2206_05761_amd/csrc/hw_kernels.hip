@@ -846,9 +846,11 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
         const int old = stale ? (int)glob(static_cast<const uint8_t*>(d.lmap))[span0] : 255;
         group_leaves<true>(d, g, code, stage + excl, big, lvl);
         glob(d.big_src)[g] = big;
-        write_level_map(d, g, lvl);
-        // a stale span this tree refines is made whole before FV1 reads it
+        // a span that lies inside one leaf of level <= L-5 in both trees,
+        // at the same level, already holds its map bytes
         const int now = (int)uniform(lvl[0]);
+        if (!(old == now && now <= d.L - 5)) write_level_map(d, g, lvl);
+        // a stale span this tree refines is made whole before FV1 reads it
         if (old <= d.L - 5 && now > d.L - 5) {
             if (d.precision == HW_FP64) fill_span<double>(d, (int)cur, span0);
             else fill_span<float>(d, (int)cur, span0);
