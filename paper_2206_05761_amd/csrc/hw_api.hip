@@ -26,7 +26,8 @@ hipError_t launch_encode_bed(Launch lc, uint32_t nblocks, int pass, int tl,
 hipError_t launch_encode_flow(int prec, Launch lc, uint32_t nblocks, int pass,
                               int tl, int cpt, bool skip, double* details, hipStream_t s);
 hipError_t launch_flag_only(int prec, Launch lc, uint32_t nblocks, hipStream_t s);
-hipError_t launch_regularise(Launch lc, uint32_t nblocks, hipStream_t s);
+hipError_t launch_regularise(Launch lc, uint32_t nblocks, int fold_pass, int tl,
+                             hipStream_t s);
 hipError_t launch_traverse(Launch lc, uint32_t nblocks, hipStream_t s);
 hipError_t launch_fv1(int prec, const Desc* descs, int n, uint32_t grid,
                       Launch fill, uint32_t fill_blocks, hipStream_t s);
@@ -335,6 +336,9 @@ struct hw_plan {
     double* d_partials = nullptr;
     // launch decomposition
     int passes = 0;
+    // five levels per pass and at least two passes: the last pass (one
+    // workgroup per problem, levels <= 4) runs inside the regularisation
+    bool fold_last = false;
     std::vector<uint32_t> enc_blocks;         // per pass
     std::vector<const uint32_t*> enc_prefix;  // per pass (device)
     uint32_t coarse_blocks = 0, trav_blocks = 0, reg_blocks = 0;
@@ -359,7 +363,7 @@ hipError_t enqueue_phase(hw_plan* pl, int phase, hipStream_t s)
     if (pl->uniform && phase != HW_PH_FV1 && phase != HW_PH_FINALIZE) return e;
     switch (phase) {
     case HW_PH_ENCODE:
-        for (int k = 0; k < pl->passes && e == hipSuccess; ++k) {
+        for (int k = 0; k < pl->passes - (pl->fold_last ? 1 : 0) && e == hipSuccess; ++k) {
             if (!pl->enc_blocks[k]) continue;
             e = hw::launch_encode_flow(pl->precision,
                                        Launch{pl->d_desc, pl->enc_prefix[k], n},
@@ -368,8 +372,8 @@ hipError_t enqueue_phase(hw_plan* pl, int phase, hipStream_t s)
         }
         break;
     case HW_PH_REGULARISE:
-        e = hw::launch_regularise(Launch{pl->d_desc, pl->reg_prefix, n},
-                                  pl->reg_blocks, s);
+        e = hw::launch_regularise(Launch{pl->d_desc, pl->reg_prefix, n}, pl->reg_blocks,
+                                  pl->fold_last ? pl->passes - 1 : -1, pl->tl, s);
         break;
     case HW_PH_TRAVERSE:
         e = hw::launch_traverse(Launch{pl->d_desc, pl->trav_prefix, n}, pl->trav_blocks, s);
@@ -673,7 +677,7 @@ int mra_flag(const hw_problem* p, const hw_buffers* b, hipStream_t stream)
     hipError_t e = hw::launch_flag_only(p->precision, Launch{dd, nullptr, 1},
                                         n_coarse_blocks(p->L), stream);
     if (e == hipSuccess)
-        e = hw::launch_regularise(Launch{dd, nullptr, 1}, n_reg_blocks(p->L), stream);
+        e = hw::launch_regularise(Launch{dd, nullptr, 1}, n_reg_blocks(p->L), -1, 0, stream);
     if (e != hipSuccess) return hip_fail(e, "flag launch");
     return ok();
 }
@@ -850,6 +854,7 @@ static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffe
 
     // decomposition and device memory: descriptors, prefixes, partials
     pl->passes = n_passes(maxL, pl->tl);
+    pl->fold_last = !uniform && pl->tl == 5 && pl->passes >= 2;
     std::vector<uint32_t> pre;  // all prefix arrays concatenated
     std::vector<size_t> enc_off(pl->passes);
     for (int k = 0; k < pl->passes; ++k) {

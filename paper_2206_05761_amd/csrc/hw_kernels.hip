@@ -610,17 +610,65 @@ __device__ inline bool regularise_block(uint32_t t, gp<const uint8_t> raw, gp<ui
     return (g0 & g1 & g2 & g3) != 0;
 }
 
+// The last encoding pass of a flow problem in its simplest form: levels
+// n_top - 1 .. 0 from the stored level n_top (0 < n_top < L), one level at
+// a time across the workgroup, with the encoder's own cell rule (children
+// in Morton order, the stored value rounded to T is the parent's child
+// value, the threshold 2^(n-L) eps, the static bed flag or-ed in), so the
+// results are the encoding pass's bit for bit.  Must be reached by the
+// whole workgroup.
+template <typename T>
+__device__ inline void encode_top_levels(const Desc& d, int n_top)
+{
+    const gp<const hw_scalars> sc = glob(static_cast<const hw_scalars*>(d.scal));
+    double smax[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) smax[v] = sc->smax[v];
+    const int L = d.L;
+    const gp<uint8_t> flags = glob(d.raw);
+    const gp<const uint8_t> zsig = glob(static_cast<const uint8_t*>(d.zsig));
+    for (int n = n_top - 1; n >= 0; --n) {
+        const uint32_t cnt = 1u << (2 * n);
+        const double thr = ldexp(d.eps, n - L);
+        for (uint32_t k = threadIdx.x; k < cnt; k += blockDim.x) {
+            bool f = false;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const gp<T> lev = glob(reinterpret_cast<T*>(d.coarse[v]));
+                const gp<const T> ch = lev + level_off(n + 1) + 4ull * k;
+                const Haar hh = haar((double)ch[0], (double)ch[1], (double)ch[2], (double)ch[3]);
+                lev[level_off(n) + k] = (T)hh.s;
+                if (significant(hh, smax[v], thr)) f = true;
+            }
+            const uint64_t o = level_off(n) + k;
+            flags[o] = (f || zsig[o]) ? 1 : 0;
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Regularisation: sig = raw of the cell or of any in-domain face neighbour
 // on the same level.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_regularise(Launch lc)
+// fold_pass >= 0 (plans, five levels per encoding pass): that last encoding
+// pass (one workgroup, levels <= 4) is not launched; the problem's first
+// workgroup here runs it first, since only its own blocks (levels 1..4)
+// read those flags.
+__global__ __launch_bounds__(kBlock) void k_regularise(Launch lc, int fold_pass, int tl)
 {
     uint32_t b;
     const int s = scen_of(lc, blockIdx.x, b);
     const Desc& d = lc.descs[s];
     if (d.scal->done) return;
     const int L = d.L;
+    if (fold_pass >= 0 && b == 0) {
+        const int n_top = L - fold_pass * tl;
+        if (n_top > 0) {
+            if (d.precision == HW_FP64) encode_top_levels<double>(d, n_top);
+            else encode_top_levels<float>(d, n_top);
+        }
+    }
     const gp<const uint8_t> raw = glob(static_cast<const uint8_t*>(d.raw));
     const gp<uint8_t> sig = glob(d.sig);
     // One thread per 2x2 Morton block of cells on levels 1..L-1; block t
@@ -2607,9 +2655,9 @@ hipError_t launch_flag_only(int prec, Launch lc, uint32_t nblocks, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_regularise(Launch lc, uint32_t nblocks, hipStream_t s)
+hipError_t launch_regularise(Launch lc, uint32_t nblocks, int fold_pass, int tl, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_regularise, dim3(nblocks), dim3(kBlock), 0, s, lc);
+    hipLaunchKernelGGL(k_regularise, dim3(nblocks), dim3(kBlock), 0, s, lc, fold_pass, tl);
     return hipGetLastError();
 }
 
