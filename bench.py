@@ -723,11 +723,12 @@ def main():
                     help="skip the uniform-FV1 comparisons")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the no-write-skip and fully wet FP64 runs")
-    ap.add_argument("--tuning", default=None, metavar="CPT,GRID[,SPARSE]",
+    ap.add_argument("--tuning", default=None, metavar="CPT,GRID[,SPARSE[,TILES]]",
                     help="fixed launch shape for the single-problem runs "
                          "(encode cells per thread, FV1 workgroups, and optionally "
-                         "1/0 for the tree-sparse finest set on/off) instead of "
-                         "the autotuner, e.g. 4,2048 or 4,1024,0")
+                         "1/0 for the tree-sparse finest set on/off, and FP32 first-pass "
+                         "tiles per workgroup) instead of the autotuner, e.g. 4,2048 or "
+                         "4,1024,0")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB three "
                          "times (reference kernel for HBM counter scaling)")
@@ -791,6 +792,8 @@ def main():
         tuning = dict(encode_cells_per_thread=vals[0], fv1_grid=vals[1])
         if len(vals) > 2:
             tuning.update(encode_skip=vals[2], fill_skip=vals[2])
+        if len(vals) > 3:
+            tuning.update(encode_tiles=vals[3])
     if args.run is not None:
         ww = getattr(W, args.run)()
         r = time_single(hw, ww, args.precision, args.steps, args.warmup, args.prof_steps,

@@ -70,7 +70,7 @@ class HwTuning(C.Structure):
     _fields_ = [("encode_cells_per_thread", C.c_int32),
                 ("fv1_block", C.c_int32), ("fv1_grid", C.c_int32),
                 ("fv1_write_skip", C.c_int32), ("encode_skip", C.c_int32),
-                ("fill_skip", C.c_int32)]
+                ("fill_skip", C.c_int32), ("encode_tiles", C.c_int32)]
 
 
 class HwStats(C.Structure):
@@ -338,7 +338,8 @@ class Plan:
                           int(tuning.get("fv1_grid", 0)),
                           int(tuning.get("fv1_write_skip", 1)),
                           int(tuning.get("encode_skip", 1)),
-                          int(tuning.get("fill_skip", 1)))
+                          int(tuning.get("fill_skip", 1)),
+                          int(tuning.get("encode_tiles", 0)))
         h = C.c_void_p()
         create = lib().hw_plan_create_uniform if uniform else lib().hw_plan_create
         _check(create(C.byref(h), self._probs, self._bufs, n,

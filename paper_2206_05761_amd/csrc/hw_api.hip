@@ -24,7 +24,8 @@ hipError_t launch_ingest(int prec, const Desc* dd, uint32_t grid,
 hipError_t launch_encode_bed(Launch lc, uint32_t nblocks, int pass, int tl,
                              int cpt, hipStream_t s);
 hipError_t launch_encode_flow(int prec, Launch lc, uint32_t nblocks, int pass,
-                              int tl, int cpt, bool skip, double* details, hipStream_t s);
+                              int tl, int cpt, bool skip, double* details, hipStream_t s,
+                              int tiles = 1);
 hipError_t launch_flag_only(int prec, Launch lc, uint32_t nblocks, hipStream_t s);
 hipError_t launch_regularise(Launch lc, uint32_t nblocks, int fold_pass, int tl,
                              hipStream_t s);
@@ -339,6 +340,9 @@ struct hw_plan {
     // five levels per pass and at least two passes: the last pass (one
     // workgroup per problem, levels <= 4) runs inside the regularisation
     bool fold_last = false;
+    // one FP32 problem, four cells per thread, no span skip: each first-pass
+    // workgroup encodes this many tiles (1: the usual form)
+    int first_tiles = 1;
     std::vector<uint32_t> enc_blocks;         // per pass
     std::vector<const uint32_t*> enc_prefix;  // per pass (device)
     uint32_t coarse_blocks = 0, trav_blocks = 0, reg_blocks = 0;
@@ -365,10 +369,11 @@ hipError_t enqueue_phase(hw_plan* pl, int phase, hipStream_t s)
     case HW_PH_ENCODE:
         for (int k = 0; k < pl->passes - (pl->fold_last ? 1 : 0) && e == hipSuccess; ++k) {
             if (!pl->enc_blocks[k]) continue;
+            const int tiles = k == 0 ? pl->first_tiles : 1;
             e = hw::launch_encode_flow(pl->precision,
                                        Launch{pl->d_desc, pl->enc_prefix[k], n},
-                                       pl->enc_blocks[k], k, pl->tl, pl->cp,
-                                       pl->encode_skip != 0, nullptr, s);
+                                       pl->enc_blocks[k] / (uint32_t)tiles, k, pl->tl, pl->cp,
+                                       pl->encode_skip != 0, nullptr, s, tiles);
         }
         break;
     case HW_PH_REGULARISE:
@@ -620,6 +625,7 @@ void hw_default_tuning(const hw_problem* p, hw_tuning* out)
     out->fv1_write_skip = 1;
     out->encode_skip = 1;
     out->fill_skip = 1;
+    out->encode_tiles = 2;
 }
 
 int hw_ingest(const hw_problem* p, const hw_buffers* b, const double* h,
@@ -843,6 +849,12 @@ static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffe
             return fail(HW_EINVAL, "fill_skip must be 0 or 1");
         }
         tu.fill_skip = tuning->fill_skip;
+        if (tuning->encode_tiles != 0 && tuning->encode_tiles != 1 &&
+            tuning->encode_tiles != 2 && tuning->encode_tiles != 4) {
+            delete pl;
+            return fail(HW_EINVAL, "encode_tiles must be 0, 1, 2 or 4");
+        }
+        if (tuning->encode_tiles != 0) tu.encode_tiles = tuning->encode_tiles;
     }
     pl->cp = tu.encode_cells_per_thread == 16 ? 2 : 1;
     pl->write_skip = tu.fv1_write_skip;
@@ -866,6 +878,11 @@ static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffe
         }
         pre.push_back(acc);
         pl->enc_blocks.push_back(acc);
+    }
+    if (!uniform && n == 1 && pl->precision == HW_FP32_BULK && pl->cp == 1 && !pl->encode_skip) {
+        const int want = tu.encode_tiles;
+        if (want > 1 && pl->enc_blocks[0] >= (uint32_t)want && pl->enc_blocks[0] % want == 0)
+            pl->first_tiles = want;
     }
     const size_t coarse_off = pre.size();
     {
@@ -1061,10 +1078,10 @@ int hw_plan_profile(hw_plan* plan, int64_t steps, double* ms_out, hipStream_t st
             if (e == hipSuccess && ph == HW_PH_ENCODE && enc_first) {
                 e = hipEventRecord(kev[0], stream);
                 for (int r = 0; r < kRepeat && e == hipSuccess; ++r)
-                    e = hw::launch_encode_flow(plan->precision,
-                                               Launch{plan->d_desc, plan->enc_prefix[0], plan->n},
-                                               plan->enc_blocks[0], 0, plan->tl, plan->cp,
-                                               plan->encode_skip != 0, nullptr, stream);
+                    e = hw::launch_encode_flow(
+                        plan->precision, Launch{plan->d_desc, plan->enc_prefix[0], plan->n},
+                        plan->enc_blocks[0] / (uint32_t)plan->first_tiles, 0, plan->tl,
+                        plan->cp, plan->encode_skip != 0, nullptr, stream, plan->first_tiles);
                 if (e == hipSuccess) e = hipEventRecord(kev[1], stream);
             }
             if (e == hipSuccess && ph == HW_PH_FV1) {

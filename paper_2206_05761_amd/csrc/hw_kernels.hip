@@ -142,13 +142,24 @@ __device__ inline bool inflow_fine(bool flowing, double y0, double y1, double dy
     return hi - lo > 0.0;
 }
 
-template <typename T, int NV, bool FLOW, bool DET, int CP, bool SKIP = false>
+// TILES > 1 (FP32 first pass over the flow variables, four cells per
+// thread, single-problem launches): each workgroup encodes TILES adjacent
+// tiles TILES b' .. TILES b' + TILES - 1, every thread one parent of each,
+// with all child loads issued first, so a workgroup has TILES times the
+// bytes in flight for the same serial chain; wave t then runs tile t's
+// remaining levels.  Each tile's cells, flags and block records are
+// computed exactly as in the one-tile form.
+template <typename T, int NV, bool FLOW, bool DET, int CP, bool SKIP = false, int TILES = 1>
 __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
                                                    int tl, double* details)
 {
     uint32_t b;
     const int s = scen_of(lc, blockIdx.x, b);
     const Desc& d = lc.descs[s];
+    constexpr bool TWO = TILES > 1;     // the multi-tile form
+    constexpr int NT = TILES;           // tiles of this workgroup
+    static_assert(NT >= 1 && NT <= 4, "one wave per tile's tail");
+    const uint32_t b0 = (uint32_t)NT * b;
     // every scalar this workgroup needs, requested together (one round trip)
     const gp<const hw_scalars> sc = glob(static_cast<const hw_scalars*>(d.scal));
     const uint32_t done = sc->done;
@@ -248,8 +259,12 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     uint8_t zr[4] = {0, 0, 0, 0}, zr2 = 0, zt[kTail];
     if (FLOW) {
         if ((uint32_t)tid < M) {
-            const uint64_t o1 = level_off(n_in - 1) + ((uint64_t)b << (2 * (lv - 1)));
-            if (CP == 1 || cp == 1) {
+            const uint64_t o1 = level_off(n_in - 1) + ((uint64_t)b0 << (2 * (lv - 1)));
+            if (TWO) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    zr[t] = zsig[o1 + ((uint64_t)t << (2 * (lv - 1))) + pidx];
+            } else if (CP == 1 || cp == 1) {
                 zr[0] = zsig[o1 + pidx];
             } else {
 #pragma unroll
@@ -257,12 +272,16 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
                 zr2 = zsig[level_off(n_in - 2) + ((uint64_t)b << (2 * (lv - 2))) + tid];
             }
         }
+        // the tail of tile t runs on wave t (lane j: cell j of each level)
+        const uint32_t tw = TWO ? (uint32_t)tid / kWave : 0u;
+        const uint32_t tj = TWO ? (uint32_t)tid & (kWave - 1u) : (uint32_t)tid;
 #pragma unroll
         for (int i = 0; i < kTail; ++i) {
             const int n = n_mid - 1 - i;
             const uint32_t c = M >> (2 * (i + 1));
-            zt[i] = (n >= n_lo && (uint32_t)tid < c) ? zsig[level_off(n) + (uint64_t)b * c + tid]
-                                                      : (uint8_t)0;
+            zt[i] = (n >= n_lo && tj < c && tw < (uint32_t)NT)
+                        ? zsig[level_off(n) + (uint64_t)(b0 + tw) * c + tj]
+                        : (uint8_t)0;
         }
     }
 
@@ -384,7 +403,36 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
         }
     }
     double p[NV];
-    if ((uint32_t)tid < M) {
+    __shared__ double lds[NT][NV][kBlock];
+    if (TWO) {
+        // every tile's children first, then each tile in turn (b names the
+        // tile for the block test and the cell indices)
+        // (the raw values are held, and widened per tile)
+        vf4 raw[NT][NV];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                raw[t][v] = __builtin_nontemporal_load(reinterpret_cast<gp<const vf4>>(
+                    src[v] + ((uint64_t)(b0 + t) << (2 * lv)) + 4ull * tid));
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            b = b0 + (uint32_t)t;
+            double cht[NV][4];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                cht[v][0] = (double)raw[t][v].x;
+                cht[v][1] = (double)raw[t][v].y;
+                cht[v][2] = (double)raw[t][v].z;
+                cht[v][3] = (double)raw[t][v].w;
+            }
+            if (blocks) block_test(cht[0]);
+            double pt[NV];
+            emit(n_in - 1, ((uint64_t)b << (2 * (lv - 1))) + pidx, cht, pt, zr[t]);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) lds[t][v][pidx] = pt[v];
+        }
+    } else if ((uint32_t)tid < M) {
         const uint64_t tile_in = (uint64_t)b << (2 * lv);
         // wave-uniform: the span's first cell, and whether the span is covered
         uint64_t wf = 0;
@@ -476,13 +524,16 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     // then the first wave alone carries on (the other waves are done): lane
     // j takes the children of cell j of the next level from LDS, and each
     // further level gathers its four children from lanes 4j..4j+3.
-    __shared__ double lds[NV][kBlock];
-    if ((uint32_t)tid < M) {
+    if (!TWO && (uint32_t)tid < M) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) lds[v][pidx] = p[v];
+        for (int v = 0; v < NV; ++v) lds[0][v][pidx] = p[v];
     }
     __syncthreads();
-    if (tid >= kWave) return;
+    // wave t finishes tile t
+    const int tw = tid / kWave;
+    if (tw >= NT) return;
+    const int tj = tid & (kWave - 1);
+    b = b0 + (uint32_t)tw;
     uint32_t cnt = M;
 #pragma unroll
     for (int i = 0; i < kTail; ++i) {
@@ -494,9 +545,9 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                ch[v][q] = i == 0 ? lds[v][(4 * tid + q) & (kBlock - 1)]
-                                  : __shfl(p[v], (4 * tid + q) & (kWave - 1));
-        if ((uint32_t)tid < cnt) emit(n, (uint64_t)b * cnt + tid, ch, p, zt[i]);
+                ch[v][q] = i == 0 ? lds[tw][v][(4 * tj + q) & (kBlock - 1)]
+                                  : __shfl(p[v], (4 * tj + q) & (kWave - 1));
+        if ((uint32_t)tj < cnt) emit(n, (uint64_t)b * cnt + tj, ch, p, zt[i]);
     }
 }
 
@@ -2633,9 +2684,25 @@ static void encode_flow_t(Launch lc, uint32_t nblocks, int pass, int tl, int cpt
     }
 }
 
+// tiles > 1: the FP32 multi-tile form of the first pass (nblocks = the
+// tiles / tiles; one problem, four cells per thread, no span skip, no
+// detail output; tiles 2 or 4).
 hipError_t launch_encode_flow(int prec, Launch lc, uint32_t nblocks, int pass,
-                              int tl, int cpt, bool skip, double* details, hipStream_t s)
+                              int tl, int cpt, bool skip, double* details, hipStream_t s,
+                              int tiles)
 {
+    if (tiles > 1) {
+        if (prec != HW_FP32_BULK || pass != 0 || cpt != 1 || skip || details || lc.n != 1 ||
+            (tiles != 2 && tiles != 4))
+            return hipErrorInvalidValue;
+        if (tiles == 2)
+            hipLaunchKernelGGL((k_encode<float, 3, true, false, 1, false, 2>), dim3(nblocks),
+                               dim3(kBlock), 0, s, lc, pass, tl, details);
+        else
+            hipLaunchKernelGGL((k_encode<float, 3, true, false, 1, false, 4>), dim3(nblocks),
+                               dim3(kBlock), 0, s, lc, pass, tl, details);
+        return hipGetLastError();
+    }
     if (prec == HW_FP64) {
         if (details) encode_flow_t<double, true>(lc, nblocks, pass, tl, cpt, skip, details, s);
         else encode_flow_t<double, false>(lc, nblocks, pass, tl, cpt, skip, details, s);

@@ -312,7 +312,11 @@ def test_launch_shapes_do_not_change_results(hw, precision):
     ref = None
     for tu in ({}, dict(encode_cells_per_thread=16, fv1_grid=8),
                dict(encode_cells_per_thread=4, fv1_grid=4096, fv1_write_skip=0),
-               dict(encode_cells_per_thread=16, fv1_grid=512)):
+               dict(encode_cells_per_thread=16, fv1_grid=512),
+               # the FP32 first pass with 1, 2 and 4 tiles per workgroup
+               dict(encode_skip=0, fill_skip=0, encode_tiles=1),
+               dict(encode_skip=0, fill_skip=0, encode_tiles=2),
+               dict(encode_skip=0, fill_skip=0, encode_tiles=4)):
         sim = _sim(hw, w, precision)
         plan = hw.Plan([sim.problem], [sim.buffers], tuning=tu)
         hw.hwfv1_run(sim.problem, sim.buffers, 30, plan=plan)
