@@ -221,12 +221,13 @@ typedef struct hw_tuning {
                                         whole when a later tree refines it
                                         and at the end of every run call;
                                         0: write every cell every step     */
-    int32_t encode_tiles;            /* FP32 plans of one problem without
+    int32_t encode_tiles;            /* plans of one problem without
                                         encode_skip, 4 cells per thread:
                                         first-pass tiles per workgroup, 1,
                                         2 or 4 (more loads in flight per
                                         workgroup, same results bit for
-                                        bit); 0 = the default              */
+                                        bit); 0 = the default (FP32 2,
+                                        FP64 1)                            */
 } hw_tuning;
 
 typedef struct hw_plan hw_plan;

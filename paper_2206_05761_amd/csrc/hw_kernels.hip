@@ -28,6 +28,7 @@
 #include "hw_device.h"
 
 #include <math.h>
+#include <type_traits>
 
 namespace hw {
 
@@ -407,24 +408,50 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     if (TWO) {
         // every tile's children first, then each tile in turn (b names the
         // tile for the block test and the cell indices)
-        // (the raw values are held, and widened per tile)
-        vf4 raw[NT][NV];
+        // (the raw values are held, and widened or paired per tile)
+        using RawT = typename std::conditional<sizeof(T) == 4, vf4, vd2>::type;
+        constexpr int RW = sizeof(T) == 4 ? 1 : 2;   // raw vectors per variable
+        RawT raw[NT][NV][RW];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                raw[t][v] = __builtin_nontemporal_load(reinterpret_cast<gp<const vf4>>(
-                    src[v] + ((uint64_t)(b0 + t) << (2 * lv)) + 4ull * tid));
+            for (int v = 0; v < NV; ++v) {
+                const uint64_t tb = (uint64_t)(b0 + t) << (2 * lv);
+                if (sizeof(T) == 4) {
+                    raw[t][v][0] = __builtin_nontemporal_load(
+                        reinterpret_cast<gp<const RawT>>(src[v] + tb + 4ull * tid));
+                } else {
+                    // the paired form: cells (2l, 2l+1) of the wave's first and
+                    // second 128 finest cells
+                    const gp<const RawT> q =
+                        reinterpret_cast<gp<const RawT>>(src[v] + tb + 256ull * wid + 2ull * lane);
+                    raw[t][v][0] = __builtin_nontemporal_load(q);
+                    raw[t][v][RW - 1] = __builtin_nontemporal_load(q + 64);
+                }
+            }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             b = b0 + (uint32_t)t;
             double cht[NV][4];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                cht[v][0] = (double)raw[t][v].x;
-                cht[v][1] = (double)raw[t][v].y;
-                cht[v][2] = (double)raw[t][v].z;
-                cht[v][3] = (double)raw[t][v].w;
+                if constexpr (sizeof(T) == 4) {
+                    cht[v][0] = (double)raw[t][v][0].x;
+                    cht[v][1] = (double)raw[t][v][0].y;
+                    cht[v][2] = (double)raw[t][v][0].z;
+                    cht[v][3] = (double)raw[t][v][0].w;
+                } else {
+                    const RawT x0 = raw[t][v][0], x1 = raw[t][v][RW - 1];
+                    const bool odd = (lane & 1u) != 0u;
+                    const RawT give = odd ? x0 : x1;
+                    RawT got;
+                    got.x = __shfl_xor(give.x, 1);
+                    got.y = __shfl_xor(give.y, 1);
+                    cht[v][0] = odd ? got.x : x0.x;
+                    cht[v][1] = odd ? got.y : x0.y;
+                    cht[v][2] = odd ? x1.x : got.x;
+                    cht[v][3] = odd ? x1.y : got.y;
+                }
             }
             if (blocks) block_test(cht[0]);
             double pt[NV];
@@ -2684,23 +2711,30 @@ static void encode_flow_t(Launch lc, uint32_t nblocks, int pass, int tl, int cpt
     }
 }
 
-// tiles > 1: the FP32 multi-tile form of the first pass (nblocks = the
-// tiles / tiles; one problem, four cells per thread, no span skip, no
-// detail output; tiles 2 or 4).
+// tiles > 1: the multi-tile form of the first pass (nblocks = the tiles /
+// tiles; one problem, four cells per thread, no span skip, no detail
+// output; tiles 2 or 4).
 hipError_t launch_encode_flow(int prec, Launch lc, uint32_t nblocks, int pass,
                               int tl, int cpt, bool skip, double* details, hipStream_t s,
                               int tiles)
 {
     if (tiles > 1) {
-        if (prec != HW_FP32_BULK || pass != 0 || cpt != 1 || skip || details || lc.n != 1 ||
-            (tiles != 2 && tiles != 4))
+        if (pass != 0 || cpt != 1 || skip || details || lc.n != 1 || (tiles != 2 && tiles != 4))
             return hipErrorInvalidValue;
-        if (tiles == 2)
+        if (prec == HW_FP64) {
+            if (tiles == 2)
+                hipLaunchKernelGGL((k_encode<double, 3, true, false, 1, false, 2>),
+                                   dim3(nblocks), dim3(kBlock), 0, s, lc, pass, tl, details);
+            else
+                hipLaunchKernelGGL((k_encode<double, 3, true, false, 1, false, 4>),
+                                   dim3(nblocks), dim3(kBlock), 0, s, lc, pass, tl, details);
+        } else if (tiles == 2) {
             hipLaunchKernelGGL((k_encode<float, 3, true, false, 1, false, 2>), dim3(nblocks),
                                dim3(kBlock), 0, s, lc, pass, tl, details);
-        else
+        } else {
             hipLaunchKernelGGL((k_encode<float, 3, true, false, 1, false, 4>), dim3(nblocks),
                                dim3(kBlock), 0, s, lc, pass, tl, details);
+        }
         return hipGetLastError();
     }
     if (prec == HW_FP64) {
