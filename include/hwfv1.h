@@ -164,7 +164,9 @@ typedef struct hw_scalars {
  *               mra_encode writes every level, the time loop (hwfv1_run,
  *               hwfv1_run_batch, hw_plan_profile) levels 0..L-2 only: the
  *               step reads a level L-1 value from its four finest children
- *               (the same value bit for bit)
+ *               (the same value bit for bit); with hw_tuning.fill_skip it
+ *               may also leave levels L-4..L-2 below a coarse leaf of level
+ *               <= L-5 unwritten (the step reads no value below a leaf)
  *   zhier       bed on levels 0..L, (4N-1)/3 FP64 (static after ingest)
  *   zsig        static bed significance flags, (N-1)/3 bytes
  *   raw         significance of the current step before regularisation

@@ -69,10 +69,12 @@ struct Desc {
 // wave of the traversal and of the copy-down).  When one leaf at level
 // <= L-5 covers a span, the copy-down writes only its groups 0, 16, 32 and
 // 48 (the cells the first encoding pass reads there, for either tile); the
-// other cells keep older values.  Such a stale span is made whole again
-// from its first cell when the next tree no longer covers it (traversal
-// emit pass), and at the end of every run call (k_densify), so outside a
-// run the current set is complete.
+// other cells keep older values, and the first encoding pass stores only
+// the span's level L-5 value (levels L-4 .. L-2 keep older values too).
+// Such a stale span, with those coarse levels, is made whole again from its
+// first cell when the next tree no longer covers it (traversal emit pass);
+// its finest cells also at the end of every run call (k_densify), so
+// outside a run the current set is complete.
 __host__ __device__ inline bool sparse_fine(const Desc& d)
 {
     return d.fill_skip && d.encode_skip && !d.full_outputs && !d.uniform && d.L >= 7;

@@ -372,12 +372,17 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     // level holds the leaf's value and every detail is 0, so each coarse
     // value is that value and each raw flag the static bed flag.  The
     // workgroup stores them (and its block records, from the same test)
-    // without the Haar sums, the LDS meet or the first wave's tail.
+    // without the Haar sums, the LDS meet or the first wave's tail.  With
+    // the tree-sparse finest set it stores the values of the tile's top
+    // level only (the next pass reads it): nothing in the step reads a level
+    // below a leaf, and when the step's tree refines the tile, the
+    // traversal's emit pass writes them (fill_span_coarse) before FV1 runs.
     if (SKIP && (CP == 1 || cp == 1) && span_skip && M == (uint32_t)kBlock) {
         const uint64_t tile_in = (uint64_t)b << (2 * lv);
         const bool tile_covered =
             uniform((int)glob(static_cast<const uint8_t*>(d.lmap))[tile_in]) <= n_lo;
         if (tile_covered) {
+            const bool top_only = sparse_fine(d);
             T val[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) val[v] = src[v][tile_in];
@@ -395,8 +400,10 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
                 cnt >>= 2;
                 if ((uint32_t)tid < cnt) {
                     const uint64_t k = (uint64_t)b * cnt + tid;
+                    if (!top_only || n == n_lo) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) dst_of(v, n)[k] = val[v];
+                        for (int v = 0; v < NV; ++v) dst_of(v, n)[k] = val[v];
+                    }
                     flags[level_off(n) + k] = zt[i] ? 1 : 0;
                 }
             }
@@ -913,6 +920,27 @@ __device__ inline void fill_span(const Desc& d, int cur, uint64_t first)
     }
 }
 
+// The coarse values of levels L-4 .. L-2 of the span starting at first
+// (the first encoding pass wrote only its level L-5 while one leaf covered
+// it): every one is the span's first finest value.  One wave.
+template <typename T>
+__device__ inline void fill_span_coarse(const Desc& d, int cur, uint64_t first)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1u);
+    const int L = d.L;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const T val = glob(reinterpret_cast<const T*>(d.fine[cur][v]))[first];
+        const gp<T> c = glob(reinterpret_cast<T*>(d.coarse[v]));
+#pragma unroll
+        for (int j = 1; j <= 3; ++j) {
+            const int n = L - 5 + j;
+            if (lane < (1u << (2 * j)))
+                c[level_off(n) + (first >> (2 * (L - n))) + lane] = val;
+        }
+    }
+}
+
 // Count pass (EMIT = false): walk, store the walk code of each group and
 // the workgroup's leaf count.  Emit pass: rebuild the leaves from the codes,
 // place them at the workgroup offset plus the in-workgroup prefix, and write
@@ -978,8 +1006,13 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
         if (!(old == now && now <= d.L - 5)) write_level_map(d, g, lvl);
         // a stale span this tree refines is made whole before FV1 reads it
         if (old <= d.L - 5 && now > d.L - 5) {
-            if (d.precision == HW_FP64) fill_span<double>(d, (int)cur, span0);
-            else fill_span<float>(d, (int)cur, span0);
+            if (d.precision == HW_FP64) {
+                fill_span<double>(d, (int)cur, span0);
+                fill_span_coarse<double>(d, (int)cur, span0);
+            } else {
+                fill_span<float>(d, (int)cur, span0);
+                fill_span_coarse<float>(d, (int)cur, span0);
+            }
         }
     }
     // a standalone traversal replaces the tree the current set was made with
