@@ -70,7 +70,8 @@ class HwTuning(C.Structure):
     _fields_ = [("encode_cells_per_thread", C.c_int32),
                 ("fv1_block", C.c_int32), ("fv1_grid", C.c_int32),
                 ("fv1_write_skip", C.c_int32), ("encode_skip", C.c_int32),
-                ("fill_skip", C.c_int32), ("encode_tiles", C.c_int32)]
+                ("fill_skip", C.c_int32), ("encode_tiles", C.c_int32),
+                ("block_list", C.c_int32)]
 
 
 class HwStats(C.Structure):
@@ -182,6 +183,15 @@ def n_hier(L):
     return int(lib().hw_n_hier(L))
 
 
+def first_descendant(leaves, L):
+    """Morton index of the first finest descendant of each hierarchy index
+    (the depth-first sort key of a leaf list)."""
+    idx = np.asarray(leaves, dtype=np.int64)
+    offs = (4 ** np.arange(L + 2, dtype=np.int64) - 1) // 3
+    n = np.searchsorted(offs, idx, side="right") - 1
+    return (idx - offs[n]) << (2 * (L - n))
+
+
 def workspace_bytes(problem: HwProblem) -> int:
     n = int(lib().hw_workspace_bytes(C.byref(problem)))
     if n == 0:
@@ -236,13 +246,25 @@ class Buffers:
         cur = self.scalars()["cur"]
         return self.fine[cur]
 
-    def leaf_list(self):
-        """The current leaf list.  When every finest cell is a leaf the time
-        loop does not write the list (it is the finest level in order)."""
+    def leaf_list_stored(self):
+        """The current leaf list as stored.  When every finest cell is a
+        leaf the time loop does not write the list (it is the finest level in
+        order).  After a plan step the whole 8 x 8 blocks of finest leaves
+        come first (block-first list); the entry points store depth-first
+        order."""
         n = int(self.scalars()["n_leaves"])
         if n == n_fine(self.problem.L):
             return (np.arange(n, dtype=np.uint64) + n_coarse(self.problem.L)).astype(np.uint32)
         return self.leaves[:n].cpu().numpy().view(np.uint32)
+
+    def leaf_list(self):
+        """The current leaves in depth-first order (Algorithm 2: ascending
+        first finest descendant), whichever order they are stored in."""
+        raw = self.leaf_list_stored()
+        key = first_descendant(raw, self.problem.L)
+        if raw.size < 2 or bool(np.all(key[1:] > key[:-1])):
+            return raw
+        return raw[np.argsort(key, kind="stable")]
 
 
 # ---- entry points (same names as the C ABI) ---------------------------------
@@ -339,7 +361,8 @@ class Plan:
                           int(tuning.get("fv1_write_skip", 1)),
                           int(tuning.get("encode_skip", 1)),
                           int(tuning.get("fill_skip", 1)),
-                          int(tuning.get("encode_tiles", 0)))
+                          int(tuning.get("encode_tiles", 0)),
+                          int(tuning.get("block_list", 1)))
         h = C.c_void_p()
         create = lib().hw_plan_create_uniform if uniform else lib().hw_plan_create
         _check(create(C.byref(h), self._probs, self._bufs, n,

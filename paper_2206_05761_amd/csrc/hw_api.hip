@@ -134,7 +134,8 @@ WorkLayout work_layout(int L)
     w.desc = o;
     o = align_up(o + sizeof(Desc));
     w.tcount = o;
-    o = align_up(o + (n_trav(L) + 1) * sizeof(uint32_t));
+    // per traversal workgroup: leaf counts, then whole finest block counts
+    o = align_up(o + 2 * (n_trav(L) + 1) * sizeof(uint32_t));
     w.big_src = o;
     o = align_up(o + n_groups(L) * sizeof(uint32_t));
     w.gcode = o;
@@ -624,6 +625,7 @@ void hw_default_tuning(const hw_problem* p, hw_tuning* out)
     out->fv1_write_skip = 1;
     out->encode_skip = 1;
     out->fill_skip = 1;
+    out->block_list = 1;
     // FP32 moves half the bytes per tile, so two tiles per workgroup keep
     // more loads in flight; FP64's paired loads already do
     out->encode_tiles = p && p->precision == HW_FP32_BULK ? 2 : 1;
@@ -856,6 +858,11 @@ static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffe
             return fail(HW_EINVAL, "encode_tiles must be 0, 1, 2 or 4");
         }
         if (tuning->encode_tiles != 0) tu.encode_tiles = tuning->encode_tiles;
+        if (tuning->block_list != 0 && tuning->block_list != 1) {
+            delete pl;
+            return fail(HW_EINVAL, "block_list must be 0 or 1");
+        }
+        tu.block_list = tuning->block_list;
     }
     pl->cp = tu.encode_cells_per_thread == 16 ? 2 : 1;
     pl->write_skip = tu.fv1_write_skip;
@@ -935,6 +942,7 @@ static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffe
         pl->host_desc.back().write_skip = pl->write_skip;
         pl->host_desc.back().encode_skip = tu.encode_skip;
         pl->host_desc.back().fill_skip = tu.fill_skip;
+        pl->host_desc.back().block_list = tu.block_list;
         pl->host_desc.back().full_outputs = 0;
         pl->host_desc.back().uniform = uniform ? 1 : 0;
     }

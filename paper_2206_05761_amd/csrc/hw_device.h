@@ -19,6 +19,9 @@ constexpr int kLeafBatch = 2;           // leaves per FV1 thread per iteration
 // taken by the light FV1 kernel for the copy-down.
 constexpr int STEP_CUR = 4;
 constexpr int STEP_DONE = 5;
+// Slot of hw_scalars.acc holding the number of whole finest blocks at the
+// head of the leaf list (written by every traversal, see block_list).
+constexpr int STEP_NBLK = 0;
 
 // Everything a kernel needs to know about one problem.  Lives in device
 // memory (the workspace for single-problem calls, the plan for batches).
@@ -62,6 +65,7 @@ struct Desc {
                            // wave span below a coarser leaf (plans only)
     int32_t fill_skip;     // the copy-down may leave spans below a coarser
                            // leaf incomplete (plans only, with encode_skip)
+    int32_t block_list;    // block-first leaf list (plans only)
 };
 
 // Tree-sparse finest set (plans, L >= 7).  A span is an aligned run of 1024
@@ -78,6 +82,19 @@ struct Desc {
 __host__ __device__ inline bool sparse_fine(const Desc& d)
 {
     return d.fill_skip && d.encode_skip && !d.full_outputs && !d.uniform && d.L >= 7;
+}
+
+// Block-first leaf list (plans, L >= 3).  The leaves of every aligned
+// 8 x 8 block of finest cells that are all leaves (a level L-3 cell whose
+// four traversal groups each hold sixteen finest leaves) come first, block
+// by block in ascending Morton order, each block's cells in Morton order;
+// the other leaves follow in depth-first order (Algorithm 2).  One wave of
+// the FV1 kernels then takes one whole block (the list's waves are aligned
+// to 64 entries).  The entry points keep the depth-first order throughout
+// (their block count is 0).
+__host__ __device__ inline bool block_list(const Desc& d)
+{
+    return d.block_list && !d.full_outputs && !d.uniform && d.L >= 3;
 }
 
 // Work decomposition of one launch: problem s owns workgroups
@@ -252,6 +269,38 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* lds,
     }
     __syncthreads();
     uint32_t excl = inc - v + lds[wid];
+    total = lds[16];
+    __syncthreads();
+    return excl;
+}
+
+// block_excl_scan on 64-bit values (lds: 17 entries).
+__device__ inline uint64_t block_excl_scan64(uint64_t v, uint64_t* lds, uint64_t& total)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    uint64_t inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint64_t w = __shfl_up(inc, o);
+        if (lane >= o) inc += w;
+    }
+    if (lane == kWave - 1) lds[wid] = inc;
+    __syncthreads();
+    if (wid == 0) {
+        const uint64_t w = lane < nw ? lds[lane] : 0ull;
+        uint64_t wi = w;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint64_t y = __shfl_up(wi, o);
+            if (lane >= o) wi += y;
+        }
+        if (lane < nw) lds[lane] = wi - w;
+        if (lane == nw - 1) lds[16] = wi;
+    }
+    __syncthreads();
+    const uint64_t excl = inc - v + lds[wid];
     total = lds[16];
     __syncthreads();
     return excl;

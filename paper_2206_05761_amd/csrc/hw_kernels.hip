@@ -24,7 +24,9 @@
 // definition (their FP64 results are bit-identical to it).  The FV1 update
 // takes one Newton-refined reciprocal where the definition divides several
 // times by the same quantity, a Newton inverse cube root for the friction
-// term, and may fuse multiply-adds, so it differs from it by rounding only.
+// term, and fused multiply-adds at fixed places (written out, so that the
+// per-leaf and the block update round alike), so it differs from it by
+// rounding only.
 #include "hw_device.h"
 
 #include <math.h>
@@ -983,10 +985,29 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     uint32_t lvl[4];
     const uint32_t cnt =
         active ? (uint32_t)group_leaves<false>(d, g, code, (uint32_t*)nullptr, big, lvl) : 0u;
-    uint32_t total;
-    const uint32_t excl = block_excl_scan(cnt, lds, total);
+    // Block-first list: the four groups of an aligned finest block (lanes
+    // 4k .. 4k+3 of one wave) whose codes all say "sixteen finest leaves"
+    // are listed in the block region, the other groups' leaves after it.
+    const bool blocks = block_list(d);
+    const uint32_t lane = threadIdx.x & (kWave - 1u);
+    bool full = false;
+    if (blocks) {
+        const uint64_t fm = __ballot(active && code == 0xFFu);
+        full = ((fm >> (lane & ~3u)) & 0xFull) == 0xFull;
+    }
+    // one scan for both counts: the group's leaves outside whole blocks in
+    // the low 16 bits (at most 4096 per workgroup), whole blocks (one per
+    // block, at its first lane) above them
+    uint32_t ptotal;
+    const uint32_t pexcl = block_excl_scan(
+        (full ? 0u : cnt) | ((full && (lane & 3u) == 0u) ? 0x10000u : 0u), lds, ptotal);
+    const uint32_t excl = pexcl & 0xffffu, total = ptotal & 0xffffu;
+    const uint32_t bexcl = pexcl >> 16, btotal = ptotal >> 16;
     if (!EMIT) {
-        if (threadIdx.x == 0) glob(d.tcount)[lb] = total;
+        if (threadIdx.x == 0) {
+            glob(d.tcount)[lb] = total;
+            if (blocks) glob(d.tcount)[d.ntrav + 1u + lb] = btotal;
+        }
         return;
     }
     // The workgroup's leaves are one contiguous run of the list: they are
@@ -998,7 +1019,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
         // same lane overwrites it below, after this load
         const uint64_t span0 = (uint64_t)(g - (threadIdx.x & (kWave - 1u))) << 4;
         const int old = stale ? (int)glob(static_cast<const uint8_t*>(d.lmap))[span0] : 255;
-        group_leaves<true>(d, g, code, stage + excl, big, lvl);
+        if (!full) group_leaves<true>(d, g, code, stage + excl, big, lvl);
         glob(d.big_src)[g] = big;
         // a span that lies inside one leaf of level <= L-5 in both trees,
         // at the same level, already holds its map bytes
@@ -1017,8 +1038,25 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     }
     // a standalone traversal replaces the tree the current set was made with
     if (d.full_outputs && lb == 0 && threadIdx.x == 0) glob(d.scal)->map_step = 0u;
+    // each group of a whole block writes its sixteen finest leaves at the
+    // block's place in the block region (the block's index: the exclusive
+    // block count at its first lane)
+    const uint32_t bpos = (uint32_t)__shfl((int)bexcl, (int)(lane & ~3u));
+    uint32_t nblk = 0u;
+    if (blocks) {
+        nblk = (uint32_t)glob(static_cast<const hw_scalars*>(d.scal))->acc[STEP_NBLK];
+        if (full) {
+            const uint32_t at =
+                64u * (glob(d.tcount)[d.ntrav + 1u + lb] + bpos) + 16u * (g & 3u);
+            const uint32_t f = (uint32_t)level_off(d.L) + 16u * g;
+            const gp<vu4> o = reinterpret_cast<gp<vu4>>(glob(d.leaves) + at);
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q)
+                o[q] = vu4{f + 4u * q, f + 4u * q + 1u, f + 4u * q + 2u, f + 4u * q + 3u};
+        }
+    }
     __syncthreads();
-    const gp<uint32_t> out = glob(d.leaves) + glob(d.tcount)[lb];
+    const gp<uint32_t> out = glob(d.leaves) + 64u * nblk + glob(d.tcount)[lb];
     for (uint32_t i = threadIdx.x; i < total; i += kBlock) out[i] = stage[i];
 }
 
@@ -1030,31 +1068,51 @@ __global__ __launch_bounds__(1024) void k_trav_scan(const Desc* descs)
     const Desc& d = descs[blockIdx.x];
     const uint32_t done = glob(d.scal)->done;
     if (!done && all_significant_step(d, lds)) {
-        if (threadIdx.x == 0) glob(d.scal)->n_leaves = 1ull << (2 * d.L);
+        if (threadIdx.x == 0) {
+            glob(d.scal)->n_leaves = 1ull << (2 * d.L);
+            glob(d.scal)->acc[STEP_NBLK] = 0.0;
+        }
         return;
     }
-    const gp<uint32_t> cnt = glob(d.tcount);
     const uint32_t n = d.ntrav;
-    // four consecutive counts per thread and round, loaded together
-    uint32_t carry = 0;
+    // With the block-first list (block_list) the counts of whole finest
+    // blocks follow the leaf counts in tcount; both are scanned, and the
+    // block total places the other leaves after the block region.
+    const bool blocks = block_list(d);
+    const gp<uint32_t> cnt = glob(d.tcount);
+    const gp<uint32_t> bcnt = cnt + n + 1u;
+    // four consecutive counts per thread and round, loaded together; both
+    // counts in one 64-bit scan (leaves in the low word, blocks above)
+    __shared__ uint64_t lds64[17];
+    uint64_t carry = 0;
     for (uint32_t base = 0; base < n; base += 4 * blockDim.x) {
         const uint32_t i0 = base + 4 * threadIdx.x;
-        uint32_t v[4];
+        uint64_t v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = i0 + k < n ? cnt[i0 + k] : 0u;
-        const uint32_t sum = (v[0] + v[1]) + (v[2] + v[3]);
-        uint32_t total;
-        uint32_t excl = carry + block_excl_scan(sum, lds, total);
+        for (int k = 0; k < 4; ++k) {
+            v[k] = i0 + k < n ? cnt[i0 + k] : 0u;
+            if (blocks && i0 + k < n) v[k] |= (uint64_t)bcnt[i0 + k] << 32;
+        }
+        const uint64_t sum = (v[0] + v[1]) + (v[2] + v[3]);
+        uint64_t total;
+        uint64_t excl = carry + block_excl_scan64(sum, lds64, total);
         if (!done) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (i0 + k < n) cnt[i0 + k] = excl;
+                if (i0 + k < n) {
+                    cnt[i0 + k] = (uint32_t)excl;
+                    if (blocks) bcnt[i0 + k] = (uint32_t)(excl >> 32);
+                }
                 excl += v[k];
             }
         }
         carry += total;
     }
-    if (threadIdx.x == 0 && !done) glob(d.scal)->n_leaves = carry;
+    if (threadIdx.x == 0 && !done) {
+        const uint64_t nblk = carry >> 32;
+        glob(d.scal)->n_leaves = 64ull * nblk + (carry & 0xffffffffull);
+        glob(d.scal)->acc[STEP_NBLK] = (double)nblk;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1089,6 +1147,7 @@ struct Fv1Ctx {
     double inlet_y0, inlet_y1, q_peak, t_peak, t_base;
     double t, dt;
     uint32_t nl;
+    uint32_t nb64;         // list entries of whole finest blocks at its head
     const double* rxy;     // LDS: dt/dx_m at [2m], dt/dy_m at [2m+1]
 };
 
@@ -1145,6 +1204,7 @@ __device__ inline void make_ctx(Fv1Ctx<T>& x, const Desc& d)
     x.t = sc->t;
     x.dt = sc->dt;
     x.nl = uniform((uint32_t)step_leaves(d, sc));
+    x.nb64 = block_list(d) ? uniform(64u * (uint32_t)sc->acc[STEP_NBLK]) : 0u;
     x.uniform = d.uniform;
 }
 
@@ -1294,10 +1354,9 @@ __device__ inline void face_flux(T hl, T unl, T utl, double zl, T hr, T unr,
                                  T utr, double zr, T g, T tol, T F[3],
                                  T& hls_out, T& hrs_out)
 {
-    // FV1 arithmetic may contract a*b+c into one fused multiply-add (its
-    // parity bar is 1e-10, not bit identity; the encoding and the
-    // significance test stay uncontracted)
-#pragma clang fp contract(fast)
+    // Fused multiply-adds are written out (fma), never left to the
+    // compiler: every caller then gets the same roundings, whatever it
+    // shares with its neighbours after inlining.
     // (fmax / fmin: maximum and minimum that return the other operand when
     // one is NaN, so a NaN depth clips to 0 as the comparison form does)
     const T dzl = (T)(zr - zl);
@@ -1314,16 +1373,17 @@ __device__ inline void face_flux(T hl, T unl, T utl, double zl, T hr, T unr,
     }
     const T cl = sqrt_nr(g * hls);
     const T cr = sqrt_nr(g * hrs);
-    const T ustar = T(0.5) * (unl + unr) + cl - cr;
-    const T cstar = T(0.5) * (cl + cr) + T(0.25) * (unl - unr);
-    const T sl = hls <= tol ? unr - T(2) * cr : fmin(unl - cl, ustar - cstar);
-    const T sr = hrs <= tol ? unl + T(2) * cl : fmax(unr + cr, ustar + cstar);
+    const T ustar = fma(T(0.5), unl + unr, cl) - cr;
+    const T cstar = fma(T(0.25), unl - unr, T(0.5) * (cl + cr));
+    const T sl = hls <= tol ? fma(T(-2), cr, unr) : fmin(unl - cl, ustar - cstar);
+    const T sr = hrs <= tol ? fma(T(2), cl, unl) : fmax(unr + cr, ustar + cstar);
+    const T hg = T(0.5) * g;
     const T ql = hls * unl;
     const T qr = hrs * unr;
     const T Ul[3] = {hls, ql, hls * utl};
-    const T Ur[3] = {hrs, qr, hrs * utr};
-    const T Fl[3] = {ql, ql * unl + T(0.5) * g * hls * hls, ql * utl};
-    const T Fr[3] = {qr, qr * unr + T(0.5) * g * hrs * hrs, qr * utr};
+    const T Ur[2] = {hrs, qr};
+    const T Fl[3] = {ql, fma(ql, unl, (hg * hls) * hls), ql * utl};
+    const T Fr[3] = {qr, fma(qr, unr, (hg * hrs) * hrs), qr * utr};
     if (sl >= T(0)) {
         F[0] = Fl[0];
         F[1] = Fl[1];
@@ -1336,9 +1396,11 @@ __device__ inline void face_flux(T hl, T unl, T utl, double zl, T hr, T unr,
         // one reciprocal of the speed difference serves the three components
         const T slsr = sl * sr;
         const T inv = rcp_nr(sr - sl);
+        // jumps of the conserved variables (the tangential one fused)
+        const T dU[3] = {Ur[0] - Ul[0], Ur[1] - Ul[1], fma(hrs, utr, -Ul[2])};
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            F[k] = ((sr * Fl[k] - sl * Fr[k]) + slsr * (Ur[k] - Ul[k])) * inv;
+            F[k] = fma(slsr, dU[k], fma(sr, Fl[k], -(sl * Fr[k]))) * inv;
     }
 }
 
@@ -1355,10 +1417,6 @@ __device__ inline double inflow_rate(const Fv1Ctx<T>& x, double t)
 template <typename T>
 __device__ inline double wave_speed(T h, T qx, T qy, T ih, T g, T tol)
 {
-    // FV1 arithmetic may contract a*b+c into one fused multiply-add (its
-    // parity bar is 1e-10, not bit identity; the encoding and the
-    // significance test stay uncontracted)
-#pragma clang fp contract(fast)
     if (!(h > tol)) return 0.0;
     const T c = sqrt_nr(g * h);
     const T u = qx * ih;
@@ -1455,18 +1513,15 @@ __device__ inline void fv1_update(const Fv1Ctx<T>& x, int m, uint32_t c, bool in
                                   T pn, T ps, T te, T tw, T tn, T ts, double dxm, double dym,
                                   uint64_t f0, uint32_t cnt, Acc& acc)
 {
-    // FV1 arithmetic may contract a*b+c into one fused multiply-add (its
-    // parity bar is 1e-10, not bit identity; the encoding and the
-    // significance test stay uncontracted)
-#pragma clang fp contract(fast)
+    // fused multiply-adds written out, as in face_flux
     const T g = (T)x.g;
     const T tol = (T)x.h_tol;
     const double dt = x.dt;
     const T rx = (T)x.rxy[2 * m];
     const T ry = (T)x.rxy[2 * m + 1];
-    T h = own.h - rx * (me - mw) - ry * (mn - ms);
-    T qx = own.qx - rx * (pe - pw) - ry * (tn - ts);
-    T qy = own.qy - rx * (te - tw) - ry * (pn - ps);
+    T h = fma(-ry, mn - ms, fma(-rx, me - mw, own.h));
+    T qx = fma(-ry, tn - ts, fma(-rx, pe - pw, own.qx));
+    T qy = fma(-ry, pn - ps, fma(-rx, te - tw, own.qy));
 
     // sources: rain, west-edge inflow, positivity, dry cells, friction
     if (x.rain_rate != 0.0) h = h + (T)(dt * x.rain_rate);
@@ -1492,9 +1547,9 @@ __device__ inline void fv1_update(const Fv1Ctx<T>& x, int m, uint32_t c, bool in
         qy = T(0);
     } else if (x.manning_n > 0.0) {
         const T nm = (T)x.manning_n;
-        const T speed = sqrt_nr(qx * qx + qy * qy) * ih;
+        const T speed = sqrt_nr(fma(qx, qx, qy * qy)) * ih;
         const T cf = g * nm * nm * inv_cbrt(h);
-        const T iden = rcp_nr(T(1) + (T)dt * cf * speed * ih);
+        const T iden = rcp_nr(fma((T)dt * cf * speed, ih, T(1)));
         qx = qx * iden;
         qy = qy * iden;
     }
@@ -1510,7 +1565,7 @@ __device__ inline void fv1_update(const Fv1Ctx<T>& x, int m, uint32_t c, bool in
     acc_max(acc, 1, fabs((double)h));
     acc_max(acc, 2, fabs((double)qx));
     acc_max(acc, 3, fabs((double)qy));
-    acc.v[4] += ((double)h * dxm) * dym;
+    acc.v[4] = fma((double)h * dxm, dym, acc.v[4]);
     if (!(isfinite((double)h) && isfinite((double)qx) && isfinite((double)qy)))
         acc.v[6] = 1.0;
 }
@@ -1520,8 +1575,7 @@ __device__ inline void fv1_update(const Fv1Ctx<T>& x, int m, uint32_t c, bool in
 template <typename T>
 __device__ inline T bed_slope_term(T hg, T h, T hc)
 {
-#pragma clang fp contract(fast)
-    return hg * (h * h - hc * hc);
+    return hg * fma(-hc, hc, h * h);
 }
 
 // fv1_update from the four face fluxes (F: the x-flux (mass, normal,
@@ -1703,14 +1757,17 @@ __device__ inline void block_face(BlockLds<T>& s, int il, int ir, bool isx, int 
 }
 
 // The full FV1 update of the 64 finest leaves of one aligned 8 x 8 Morton
-// block (cells c0 .. c0 + 63 of a problem whose leaves are all finest,
-// L >= 3), by one wave.  The result is fv1_leaf's for each cell: every face
-// flux is the same call with the same arguments, made once per face instead
-// of once from each side (144 faces for 64 cells instead of 256: each lane's
-// west face, each lane's south face, then the 16 faces on the block's east
-// and north edges), and each cell's velocities are formed once instead of
-// once per face that uses them.
-template <typename T>
+// block (cells c0 .. c0 + 63, L >= 3), by one wave.  The result is
+// fv1_leaf's for each cell: every face flux is the same call with the same
+// arguments, made once per face instead of once from each side (144 faces
+// for 64 cells instead of 256: each lane's west face, each lane's south
+// face, then the 16 faces on the block's east and north edges), and each
+// cell's velocities are formed once instead of once per face that uses
+// them.  MIXED: the problem has coarser leaves this step, so a face
+// neighbour outside the block may lie inside one; its leaf-level byte then
+// names that leaf, whose values replace the finest ones (fv1_leaf's
+// neighbour rule).  Otherwise every leaf is finest.
+template <typename T, bool MIXED>
 __device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, BlockLds<T>& s,
                                  const BlockConst& kc)
 {
@@ -1733,7 +1790,10 @@ __device__ inline void fv1_block(const Fv1Ctx<T>& x, uint32_t c0, Acc& acc, Bloc
                        : in ? morton((uint32_t)nI, (uint32_t)nJ) : c0 + morton(kc.ei, kc.ej);
     const Cell<T> own = load_fine<T>(x, c);
     Cell<T> hc = load_fine<T>(x, src);
+    int lv = L;
+    if (MIXED && in && lane < 32u) lv = x.lmap[src];
     __builtin_amdgcn_sched_barrier(0);
+    if (MIXED && lv < L) hc = load_cell<T>(x, lv, src >> (2 * (L - lv)));
     if (!in && lane < 32u) {
         const int dir = (int)((lane >> 3) & 3u);
         const bool wall = (dir == HW_W && x.bc[HW_W] == HW_BC_WALL) ||
@@ -2018,6 +2078,28 @@ __device__ inline bool light_history(const Fv1Ctx<T>& x, bool ok, int m, uint32_
     return light_history_block<T>(x, block, c0, dry, e);
 }
 
+// Super-chunks of a problem's block region (whole finest blocks at the head
+// of a block-first list, which the heavy kernel updates at a fraction of
+// the per-leaf cost): 0 when every leaf is finest or the list has none.
+__device__ inline uint32_t block_chunks(const Desc& d, const hw_scalars* sc, bool fin)
+{
+    if (fin || !block_list(d)) return 0u;
+    return (64u * (uint32_t)sc->acc[STEP_NBLK]) / (uint32_t)(kLeafBatch * kBlock);
+}
+
+// Order in which the schedule visits a problem's nc super-chunks: the nbc
+// chunks of the block region and the others interleaved in proportion
+// (visit v takes block chunk floor(v nbc / nc) when that count steps up,
+// else the next other chunk), so that each XCD's contiguous segment of the
+// schedule holds its share of both kinds, each kind in list order.
+__device__ inline uint32_t chunk_order(uint32_t v, uint32_t nbc, uint32_t nc)
+{
+    if (nbc == 0u || nbc >= nc) return v;
+    const uint32_t b = (uint32_t)(((uint64_t)v * nbc) / nc);
+    const bool blk = (uint32_t)(((uint64_t)(v + 1u) * nbc) / nc) > b;
+    return blk ? b : nbc + (v - b);
+}
+
 // Chunk bookkeeping shared by the two FV1 kernels: the leaves of every
 // problem are cut into super-chunks of kLeafBatch * kBlock leaves; the
 // super-chunk sequence of all problems is split into 8 contiguous segments,
@@ -2044,7 +2126,7 @@ enum { kAllProblems = 0, kFinestOnly = 1, kMixedOnly = 2 };
 // finest.
 __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre,
                                         int mode = kAllProblems, uint8_t* mine = nullptr,
-                                        uint8_t* finest = nullptr)
+                                        uint8_t* finest = nullptr, uint32_t* cblk = nullptr)
 {
     constexpr uint32_t SC = kLeafBatch * kBlock;
     if (threadIdx.x == 0) {
@@ -2057,6 +2139,7 @@ __device__ inline Fv1Sched fv1_schedule(const Desc* descs, int n, uint32_t* cpre
             const bool fin = all_finest(descs[s], nl);
             if (mine) mine[s] = m ? 1 : 0;
             if (finest) finest[s] = fin ? 1 : 0;
+            if (cblk) cblk[s] = block_chunks(descs[s], sc, fin);
             const bool take = m && (mode == kAllProblems || (mode == kFinestOnly) == fin);
             a += take ? ((uint32_t)nl + SC - 1) / SC : 0u;
         }
@@ -2206,7 +2289,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
         const Fv1Sched f =
             fv1_schedule(descs, n, cpre, fin ? kFinestOnly : kMixedOnly, mine, finest);
         int cs = -1;
-        uint32_t c0 = 0, c1 = 0;
+        uint32_t c0 = 0, c1 = 0, nbc = 0;
         for (uint32_t ch = f.c_begin; ch < f.c_end; ch += f.g8) {
             if (cs < 0 || ch >= c1) {
                 int s = cs < 0 ? 0 : cs;
@@ -2218,6 +2301,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
                 wetb = glob(descs[s].wet);
                 c0 = uniform(cpre[s]);
                 c1 = uniform(cpre[s + 1]);
+                nbc = fin ? 0u : uniform(block_chunks(descs[s], descs[s].scal, false));
             }
             if (fin && x.L >= 5 && !x.uniform) {
                 // up to 32 of this workgroup's super-chunks at once, all of the
@@ -2229,7 +2313,9 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
                 ch += (cnt - 1u) * f.g8;
                 continue;
             }
-            const uint32_t sc = ch - c0;
+            // the super-chunk this visit takes (the heavy kernel visits in
+            // the same order)
+            const uint32_t sc = chunk_order(ch - c0, nbc, c1 - c0);
             const uint32_t base = sc * SC;
             LightBatch<T> b;
             uint32_t bits = 0;
@@ -2303,6 +2389,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
     __shared__ double red[kBlock / kWave][kPartial];
     __shared__ double rxy[2 * (HW_MAX_L + 1)];
     __shared__ const uint8_t* wtab[kMaxScen];
+    __shared__ uint32_t cblk[kMaxScen];
     __shared__ BlockLds<T> blds[kBlock / kWave];
     const BlockConst kc = block_const();
     const int tid = threadIdx.x;
@@ -2310,7 +2397,8 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
     const int lane = tid & (kWave - 1);
     for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
     if (tid < n) wtab[tid] = descs[tid].wet;
-    const Fv1Sched f = fv1_schedule(descs, n, cpre);   // ends with a barrier
+    // ends with a barrier
+    const Fv1Sched f = fv1_schedule(descs, n, cpre, kAllProblems, nullptr, nullptr, cblk);
     const uint32_t K = f.c_begin < f.c_end ? (f.c_end - f.c_begin + f.g8 - 1) / f.g8 : 0u;
     Acc acc;
     acc_reset(acc);
@@ -2328,7 +2416,8 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
                 if (cpre[mid] <= ch) lo = mid;
                 else hi = mid - 1;
             }
-            word = *reinterpret_cast<gp<const uint32_t>>(glob(wtab[lo]) + 4ull * (ch - cpre[lo]));
+            const uint32_t sc = chunk_order(ch - cpre[lo], cblk[lo], cpre[lo + 1] - cpre[lo]);
+            word = *reinterpret_cast<gp<const uint32_t>>(glob(wtab[lo]) + 4ull * sc);
         }
         uint64_t mask = __ballot(word != 0u);
         while (mask) {
@@ -2352,7 +2441,7 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
             // The marked sub-chunks of this super-chunk (bit u of byte w: the
             // 64 leaves base + u kBlock + w kWave + lane) are dealt to the
             // workgroup's waves in turn, whichever wave's position they hold.
-            const uint32_t base = (ch - c0) * SC;
+            const uint32_t base = chunk_order(ch - c0, cblk[cs], c1 - c0) * SC;
             const bool finest = (uint64_t)x.nl == (1ull << (2 * x.L));
             const uint32_t fin_off = (uint32_t)level_off(x.L);
             const uint32_t lane_mask = (1u << kLeafBatch) - 1u;
@@ -2361,6 +2450,15 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
             for (int w = 0; w < kBlock / kWave; ++w)
                 items |= ((wj >> (8 * w)) & lane_mask) << (kLeafBatch * w);
             items = uniform(items);
+            // first list entries of the super-chunk's sub-chunks that lie in
+            // the block region (lane kLeafBatch w + u: sub-chunk u of wave
+            // position w), one load for all of them
+            uint32_t lfv = 0u;
+            if (!finest && base < x.nb64 && lane < kLeafBatch * (kBlock / kWave)) {
+                const uint32_t p = base + (uint32_t)(lane % kLeafBatch) * kBlock +
+                                   (uint32_t)(lane / kLeafBatch) * kWave;
+                if (p < x.nb64) lfv = ld_off(x.leaves, p * 4u);
+            }
             int k = 0;
 #pragma unroll 1
             while (items) {
@@ -2369,10 +2467,18 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
                 if ((k++ & (kBlock / kWave - 1)) != wid) continue;
                 const uint32_t w = (uint32_t)bit / kLeafBatch, u = (uint32_t)bit % kLeafBatch;
                 const uint32_t leaf = base + u * kBlock + w * kWave + (uint32_t)lane;
+                // the wave's first list entry
+                const uint32_t p0 = base + u * kBlock + w * kWave;
+                // a whole finest block at the head of a block-first list
+                // (its first cell aligned, as the traversal writes it)
+                const uint32_t lf = (uint32_t)__builtin_amdgcn_readlane((int)lfv, bit);
+                const bool blk = !finest && p0 < x.nb64 && lf >= fin_off &&
+                                 ((lf - fin_off) & 63u) == 0u;
                 if (finest && x.L >= 3) {
                     // one aligned 8 x 8 block of finest leaves per wave
-                    const uint32_t c0 = base + u * kBlock + w * kWave;
-                    if (c0 < x.nl) fv1_block<T>(x, c0, acc, blds[wid], kc);
+                    if (p0 < x.nl) fv1_block<T, false>(x, p0, acc, blds[wid], kc);
+                } else if (blk) {
+                    fv1_block<T, true>(x, lf - fin_off, acc, blds[wid], kc);
                 } else if (leaf < x.nl) {
                     if (finest) fv1_leaf<T, true>(x, fin_off + leaf, acc);
                     else fv1_leaf<T, false>(x, x.leaves[leaf], acc);

@@ -144,3 +144,26 @@ def compare_leaf_lists(L, got, want, ties, log=print):
     log(f"  leaf lists differ only inside the tie band "
         f"({int((a != b).sum())} finest cells)")
     return int(ties.size)
+
+
+def check_block_first(L, stored, canon):
+    """Layout of a plan's block-first leaf list against the depth-first
+    list of the same leaves: first every aligned 64-cell block whose finest
+    cells are all leaves, in ascending order, each in Morton order; then
+    the other leaves in depth-first order.  Returns the number of whole
+    blocks."""
+    off = (4 ** L - 1) // 3
+    canon = np.asarray(canon, dtype=np.int64)
+    stored = np.asarray(stored, dtype=np.int64)
+    assert stored.size == canon.size
+    fin = canon[canon >= off] - off
+    blk, cnt = np.unique(fin >> 6, return_counts=True)
+    full = blk[cnt == 64]
+    nb = int(full.size)
+    head = (off + (full[:, None] << 6) + np.arange(64)[None, :]).ravel()
+    assert np.array_equal(stored[:64 * nb], head)
+    in_full = np.zeros(canon.size, dtype=bool)
+    f = canon >= off
+    in_full[f] = np.isin((canon[f] - off) >> 6, full)
+    assert np.array_equal(stored[64 * nb:], canon[~in_full])
+    return nb

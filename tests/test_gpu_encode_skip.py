@@ -17,10 +17,13 @@ set.  Checks:
   the cells of spans below one leaf of the previous tree that the next
   encoding does not read are overwritten with different values (with
   encode_skip alone: only spans the next tree covers too, since the FV1
-  update reads finest values of its finest leaves).  The run still equals
-  an untouched one bit for bit, and with both skips off it does not.  In
-  the fill_skip case the poisoned spans that the next tree refines must be
-  completed by the traversal, and some are.
+  update reads finest values of its finest leaves).  With both skips the
+  coarse values of levels L-4 .. L-2 of those spans are poisoned as well
+  (the first encoding pass stores only level L-5 of a tile one leaf
+  covers).  The run still equals an untouched one bit for bit, and with
+  both skips off it does not.  In the fill_skip case the poisoned spans
+  that the next tree refines must be completed by the traversal, and some
+  are.
 """
 import sys
 
@@ -198,6 +201,25 @@ def _poison(sim, spans, span_log4, offsets):
     return int(idx.size)
 
 
+def _poison_coarse(sim, spans, L):
+    """Overwrite the coarse values of levels L-4 .. L-2 below each span of
+    1024 finest cells (a level L-5 cell)."""
+    import torch
+    idx = []
+    for j in (1, 2, 3):
+        n = L - 5 + j
+        idx.append(((4 ** n - 1) // 3 + spans[:, None] * 4 ** j
+                    + np.arange(4 ** j)[None, :]).ravel())
+    idx = np.concatenate(idx)
+    torch.cuda.synchronize()
+    if idx.size:
+        t = torch.from_numpy(idx).to(sim.buffers.coarse[0].device)
+        for v, d in enumerate((2.0, -1.0, 0.75)):
+            sim.buffers.coarse[v][t] += d
+    torch.cuda.synchronize()
+    return int(idx.size)
+
+
 @pytest.mark.parametrize("dry", [False, True])
 @pytest.mark.parametrize("mode", ["encode", "both"])
 @pytest.mark.parametrize("cells", [4, 16])
@@ -226,6 +248,9 @@ def test_skipped_cells_are_read_by_nobody(hw, cells, mode, dry):
             refined += int(np.setdiff1d(prev, nxt).size)
             poisoned += _poison(on, sp, k, offsets)
             _poison(off_, sp, k, offsets)
+            if mode == "both":
+                poisoned += _poison_coarse(on, sp, L)
+                _poison_coarse(off_, sp, L)
         for sim, plan in ((on, pon), (off_, poff)):
             hw.hwfv1_run(sim.problem, sim.buffers, 1, plan=plan)
     log("  poisoned cells", poisoned, "spans refined by the next tree", refined,
