@@ -174,6 +174,14 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     const uint64_t step = sc->step;
     const uint32_t map_step = sc->map_step;
     const uint64_t n_leaves = sc->n_leaves;
+    // (span-skip form of the first pass) the leaf-level byte of the tile's
+    // first cell, requested with the scalars; used only when the map
+    // describes the previous tree (tile of 4^min(L, tl) cells, in bounds)
+    uint32_t map0 = 255u;
+    if (SKIP && FLOW && pass == 0 && d.encode_skip) {
+        const int lv0 = d.L < tl ? d.L : tl;
+        map0 = glob(static_cast<const uint8_t*>(d.lmap))[(uint64_t)b << (2 * lv0)];
+    }
     if (FLOW && done) return;
     const int L = d.L;
     const int n_in = L - pass * tl;
@@ -381,8 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(Launch lc, int pass,
     // traversal's emit pass writes them (fill_span_coarse) before FV1 runs.
     if (SKIP && (CP == 1 || cp == 1) && span_skip && M == (uint32_t)kBlock) {
         const uint64_t tile_in = (uint64_t)b << (2 * lv);
-        const bool tile_covered =
-            uniform((int)glob(static_cast<const uint8_t*>(d.lmap))[tile_in]) <= n_lo;
+        const bool tile_covered = uniform((int)map0) <= n_lo;
         if (tile_covered) {
             const bool top_only = sparse_fine(d);
             T val[NV];
