@@ -46,10 +46,10 @@
  *      leaves            hierarchy Z-order index (uint32) of every leaf in
  *                        ascending order of its first finest descendant
  *                        (= depth-first order of Algorithm 2), capacity N;
- *                        after a plan step with hw_tuning.block_list (the
- *                        default) every aligned 8 x 8 block of finest
- *                        leaves comes first, block by block in that order,
- *                        and the other leaves follow in that order.
+ *                        after a plan step that uses hw_tuning.block_list
+ *                        every aligned 8 x 8 block of finest leaves comes
+ *                        first, block by block in that order, and the other
+ *                        leaves follow in that order.
  *    Row-major host-side fields are [j][i], j the row (y), i the column (x).
  *  - Precision: HW_FP64 keeps h, qx, qy in FP64; HW_FP32_BULK stores and
  *    updates them in FP32 while the significance test, the bed hierarchy,
@@ -234,12 +234,15 @@ typedef struct hw_tuning {
                                         workgroup, same results bit for
                                         bit); 0 = the default (FP32 2,
                                         FP64 1)                            */
-    int32_t block_list;              /* 1: the traversal lists the leaves
-                                        of every aligned 8 x 8 block of
-                                        finest leaves first, and FV1
-                                        updates each such block with one
-                                        wave through LDS (same results bit
-                                        for bit); 0: depth-first list,
+    int32_t block_list;              /* 1: in a step whose whole aligned
+                                        8 x 8 blocks of finest leaves hold
+                                        at least 2^19 leaves, the traversal
+                                        lists those blocks first and FV1
+                                        updates each with one wave through
+                                        LDS (same results bit for bit;
+                                        with fewer, the depth-first order
+                                        is faster); 2: whenever there is a
+                                        whole block; 0: depth-first list,
                                         every leaf updated on its own      */
 } hw_tuning;
 

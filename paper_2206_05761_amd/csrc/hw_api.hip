@@ -858,9 +858,9 @@ static int plan_create(hw_plan** out, const hw_problem* problems, const hw_buffe
             return fail(HW_EINVAL, "encode_tiles must be 0, 1, 2 or 4");
         }
         if (tuning->encode_tiles != 0) tu.encode_tiles = tuning->encode_tiles;
-        if (tuning->block_list != 0 && tuning->block_list != 1) {
+        if (tuning->block_list < 0 || tuning->block_list > 2) {
             delete pl;
-            return fail(HW_EINVAL, "block_list must be 0 or 1");
+            return fail(HW_EINVAL, "block_list must be 0, 1 or 2");
         }
         tu.block_list = tuning->block_list;
     }

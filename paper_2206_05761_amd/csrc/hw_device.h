@@ -65,7 +65,9 @@ struct Desc {
                            // wave span below a coarser leaf (plans only)
     int32_t fill_skip;     // the copy-down may leave spans below a coarser
                            // leaf incomplete (plans only, with encode_skip)
-    int32_t block_list;    // block-first leaf list (plans only)
+    int32_t block_list;    // block-first leaf list (plans only): 0 never,
+                           // 1 when whole blocks hold at least 2^19 leaves,
+                           // 2 whenever there is one
 };
 
 // Tree-sparse finest set (plans, L >= 7).  A span is an aligned run of 1024
@@ -90,8 +92,10 @@ __host__ __device__ inline bool sparse_fine(const Desc& d)
 // by block in ascending Morton order, each block's cells in Morton order;
 // the other leaves follow in depth-first order (Algorithm 2).  One wave of
 // the FV1 kernels then takes one whole block (the list's waves are aligned
-// to 64 entries).  The entry points keep the depth-first order throughout
-// (their block count is 0).
+// to 64 entries).  The traversal's scan takes this layout when whole blocks
+// hold enough leaves (Desc.block_list), else the depth-first one; the
+// entry points keep the depth-first order throughout (their block count is
+// 0).
 __host__ __device__ inline bool block_list(const Desc& d)
 {
     return d.block_list && !d.full_outputs && !d.uniform && d.L >= 3;

@@ -1021,12 +1021,23 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     // staged in LDS at their in-workgroup offsets and then written with
     // consecutive lanes on consecutive entries.
     __shared__ uint32_t stage[kBlock * 16];
+    // The scan chose the layout: block-first (nblk whole blocks head the
+    // list) or, with nblk = 0, depth-first, where a group's leaves follow
+    // the other leaves and the whole blocks before it in the workgroup
+    // (bpos: the whole blocks before its block, from the block's first lane).
+    const uint32_t bpos = (uint32_t)__shfl((int)bexcl, (int)(lane & ~3u));
+    const uint32_t nblk =
+        blocks ? (uint32_t)glob(static_cast<const hw_scalars*>(d.scal))->acc[STEP_NBLK] : 0u;
+    const bool bfirst = nblk != 0u;
     if (active) {
         // the map byte of the wave's span as the previous tree left it; the
         // same lane overwrites it below, after this load
         const uint64_t span0 = (uint64_t)(g - (threadIdx.x & (kWave - 1u))) << 4;
         const int old = stale ? (int)glob(static_cast<const uint8_t*>(d.lmap))[span0] : 255;
-        if (!full) group_leaves<true>(d, g, code, stage + excl, big, lvl);
+        if (!(full && bfirst)) {
+            const uint32_t at = bfirst ? excl : excl + 64u * bpos + (full ? 16u * (g & 3u) : 0u);
+            group_leaves<true>(d, g, code, stage + at, big, lvl);
+        }
         glob(d.big_src)[g] = big;
         // a span that lies inside one leaf of level <= L-5 in both trees,
         // at the same level, already holds its map bytes
@@ -1045,27 +1056,26 @@ __global__ __launch_bounds__(kBlock) void k_traverse(Launch lc)
     }
     // a standalone traversal replaces the tree the current set was made with
     if (d.full_outputs && lb == 0 && threadIdx.x == 0) glob(d.scal)->map_step = 0u;
-    // each group of a whole block writes its sixteen finest leaves at the
-    // block's place in the block region (the block's index: the exclusive
-    // block count at its first lane)
-    const uint32_t bpos = (uint32_t)__shfl((int)bexcl, (int)(lane & ~3u));
-    uint32_t nblk = 0u;
-    if (blocks) {
-        nblk = (uint32_t)glob(static_cast<const hw_scalars*>(d.scal))->acc[STEP_NBLK];
-        if (full) {
-            const uint32_t at =
-                64u * (glob(d.tcount)[d.ntrav + 1u + lb] + bpos) + 16u * (g & 3u);
-            const uint32_t f = (uint32_t)level_off(d.L) + 16u * g;
-            const gp<vu4> o = reinterpret_cast<gp<vu4>>(glob(d.leaves) + at);
+    // block-first: each group of a whole block writes its sixteen finest
+    // leaves at the block's place in the block region
+    const uint32_t boff = blocks ? glob(d.tcount)[d.ntrav + 1u + lb] : 0u;
+    if (bfirst && full) {
+        const uint32_t at = 64u * (boff + bpos) + 16u * (g & 3u);
+        const uint32_t f = (uint32_t)level_off(d.L) + 16u * g;
+        const gp<vu4> o = reinterpret_cast<gp<vu4>>(glob(d.leaves) + at);
 #pragma unroll
-            for (uint32_t q = 0; q < 4; ++q)
-                o[q] = vu4{f + 4u * q, f + 4u * q + 1u, f + 4u * q + 2u, f + 4u * q + 3u};
-        }
+        for (uint32_t q = 0; q < 4; ++q)
+            o[q] = vu4{f + 4u * q, f + 4u * q + 1u, f + 4u * q + 2u, f + 4u * q + 3u};
     }
     __syncthreads();
-    const gp<uint32_t> out = glob(d.leaves) + 64u * nblk + glob(d.tcount)[lb];
-    for (uint32_t i = threadIdx.x; i < total; i += kBlock) out[i] = stage[i];
+    const uint32_t n_out = bfirst ? total : total + 64u * btotal;
+    const gp<uint32_t> out = glob(d.leaves) + glob(d.tcount)[lb] + 64u * (bfirst ? nblk : boff);
+    for (uint32_t i = threadIdx.x; i < n_out; i += kBlock) out[i] = stage[i];
 }
+
+// Leaves in whole finest blocks from which a plan step lists them first
+// (hw_tuning.block_list = 1; 2 lists any).
+constexpr uint64_t kBlockListMin = 1ull << 19;
 
 // Exclusive scan of the per-workgroup leaf counts of one problem (one
 // workgroup per problem); the total is the leaf count of the step.
@@ -1118,7 +1128,12 @@ __global__ __launch_bounds__(1024) void k_trav_scan(const Desc* descs)
     if (threadIdx.x == 0 && !done) {
         const uint64_t nblk = carry >> 32;
         glob(d.scal)->n_leaves = 64ull * nblk + (carry & 0xffffffffull);
-        glob(d.scal)->acc[STEP_NBLK] = (double)nblk;
+        // the block-first layout only when whole blocks hold enough leaves
+        // (with few, the FV1 kernels' chunks are few and each one a
+        // workgroup's serial chain; the depth-first order, which spreads the
+        // costly leaves over all chunks, is then faster)
+        const uint64_t lo = d.block_list == 2 ? 1ull : kBlockListMin;
+        glob(d.scal)->acc[STEP_NBLK] = 64ull * nblk >= lo ? (double)nblk : 0.0;
     }
 }
 

@@ -4,7 +4,8 @@ A plan's traversal lists the leaves of every aligned 8 x 8 block of finest
 leaves first (block by block, ascending Morton order), then the other
 leaves in depth-first order, so that the FV1 kernels update a whole block
 per wave through the staged block update (with coarser face neighbours
-taken from the leaf-level map).  The entry points keep the depth-first list
+taken from the leaf-level map): hw_tuning.block_list = 2 whenever there is
+such a block, the default 1 from 2^19 leaves in them.  The entry points keep the depth-first list
 and update every leaf on its own.  Checks, step by step on mixed trees:
 
 * the stored list has exactly that layout: its head holds every whole
@@ -65,7 +66,7 @@ def test_plan_steps_equal_entry_point_steps(hw, name, precision):
     log(f"[block list] {name} {precision}")
     a = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision=precision)
     b = hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision=precision)
-    plan = hw.Plan([a.problem], [a.buffers], tuning=dict(fv1_write_skip=1))
+    plan = hw.Plan([a.problem], [a.buffers], tuning=dict(fv1_write_skip=1, block_list=2))
     blocks = mixed = 0
     for k in range(40):
         hw.hwfv1_run(a.problem, a.buffers, 1, plan=plan)
@@ -95,23 +96,26 @@ def test_plan_steps_equal_entry_point_steps(hw, name, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
-def test_block_list_on_and_off_agree(hw, precision):
-    """hw_tuning.block_list = 0 keeps the depth-first list and the per-leaf
-    update; both plans give the same leaves, fields and scalars bit for bit
-    (a batch of two problems, so the interleaved chunk order of the FV1
+def test_block_list_modes_agree(hw, precision):
+    """hw_tuning.block_list = 2 lists the whole blocks first whenever there
+    is one; 1 (the default) only when they hold at least 2^19 leaves, so
+    these small problems keep the depth-first list (the emit pass then
+    places the counted whole blocks in depth-first order); 0 never counts
+    them.  All three plans give the same leaves, fields and scalars bit for
+    bit (a batch of two problems, so the interleaved chunk order of the FV1
     kernels covers more than one problem)."""
     ws = [W.circular_dambreak_flat(9), W.dambreak_bumps_l6(L=8)]
-    log(f"[block list] on/off {precision}")
+    log(f"[block list] modes {precision}")
     runs = []
-    for on in (1, 0):
+    for mode in (2, 1, 0):
         sims = [hw.Simulation(w.params, w.h, w.qx, w.qy, w.z, precision=precision) for w in ws]
         plan = hw.Plan([s.problem for s in sims], [s.buffers for s in sims],
-                       tuning=dict(block_list=on))
+                       tuning=dict(block_list=mode))
         hw.hwfv1_run_batch(plan, 30, stats=False)
         for s, w in zip(sims, ws):
             stored = s.buffers.leaf_list_stored()
             canon = s.buffers.leaf_list()
-            if on:
+            if mode == 2:
                 assert check_block_first(w.L, stored, canon) > 0
             else:
                 assert np.array_equal(stored, canon)
@@ -119,9 +123,10 @@ def test_block_list_on_and_off_agree(hw, precision):
         plan.close()
         for s in sims:
             s.close()
-    for (ea, sa, la), (eb, sb, lb) in zip(*runs):
-        for x, y in zip(ea, eb):
-            assert np.array_equal(x, y)
-        assert np.array_equal(la, lb)
-        for key in ("t", "dt", "step", "n_leaves", "maxspeed", "clips"):
-            assert sa[key] == sb[key], key
+    for other in runs[1:]:
+        for (ea, sa, la), (eb, sb, lb) in zip(runs[0], other):
+            for x, y in zip(ea, eb):
+                assert np.array_equal(x, y)
+            assert np.array_equal(la, lb)
+            for key in ("t", "dt", "step", "n_leaves", "maxspeed", "clips"):
+                assert sa[key] == sb[key], key
