@@ -38,7 +38,7 @@ hipError_t launch_fv1_only(int prec, const Desc* descs, int n, uint32_t grid, hi
 hipError_t launch_fv1_heavy(int prec, const Desc* descs, int n, uint32_t grid, hipStream_t s);
 hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, uint32_t grid,
                        hipStream_t s);
-hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t s);
+hipError_t launch_finalize(int prec, const Desc* descs, int n, uint32_t grid, hipStream_t s);
 hipError_t launch_forget(const Desc* dd, uint64_t nhist, hipStream_t s);
 hipError_t launch_densify(int prec, const Desc* dd, int L, hipStream_t s);
 // One thread waits until `ticks` of the constant-rate wall clock have
@@ -394,7 +394,7 @@ hipError_t enqueue_phase(hw_plan* pl, int phase, hipStream_t s)
         break;
     case HW_PH_FINALIZE:
         // a uniform FV1 plan has no copy-down: it finalises on its own
-        if (pl->uniform) e = hw::launch_finalize(pl->d_desc, n, pl->fv1_grid, s);
+        if (pl->uniform) e = hw::launch_finalize(pl->precision, pl->d_desc, n, pl->fv1_grid, s);
         break;
     }
     return e;

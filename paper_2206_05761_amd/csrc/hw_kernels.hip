@@ -1509,6 +1509,34 @@ __device__ inline void acc_flush(Acc& a, double (*red)[kPartial], double* rec)
     acc_reset(a);
 }
 
+// acc_flush into a record of its own in global memory (written once: the
+// record takes the workgroup's values, not combined with what it held).
+// Must be reached by the whole workgroup.
+__device__ inline void acc_flush_store(Acc& a, double (*red)[kPartial], gp<double> out)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < kPartial; ++q) {
+        const double x = slot_is_sum(q) ? wave_sum(a.v[q]) : wave_max(a.v[q]);
+        if (lane == 0) red[wid][q] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < kPartial) {
+        const int q = threadIdx.x;
+        const int nw = blockDim.x / kWave;
+        const bool sum = slot_is_sum(q);
+        double r = red[0][q];
+        for (int w = 1; w < nw; ++w) {
+            const double y = red[w][q];
+            r = sum ? r + y : (y > r ? y : r);
+        }
+        out[q] = r;
+    }
+    __syncthreads();
+    acc_reset(a);
+}
+
 // Finest cell k of the current set (the all-finest form of load_cell).
 template <typename T>
 __device__ inline Cell<T> load_fine(const Fv1Ctx<T>& x, uint32_t k)
@@ -2402,12 +2430,16 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
 // no wet super-chunk costs one round trip.  Every wave of a workgroup reads
 // the same words and so visits the same super-chunks, in ascending order.
 // Records go to slots [rec0, rec0 + gridDim.x).
+// Held to four waves per SIMD.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ descs, int n, uint32_t rec0)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_fv1_heavy(const Desc* __restrict__ descs, int n, uint32_t rec0)
 {
     constexpr uint32_t SC = kLeafBatch * kBlock;
+    // (no LDS records per problem: a workgroup visits the problems in
+    // ascending order, each once, and writes each record when it leaves
+    // that problem, so the LDS fits four workgroups per CU)
     __shared__ uint32_t cpre[kMaxScen + 1];
-    __shared__ double rec[kMaxScen][kPartial];
     __shared__ double red[kBlock / kWave][kPartial];
     __shared__ double rxy[2 * (HW_MAX_L + 1)];
     __shared__ const uint8_t* wtab[kMaxScen];
@@ -2417,7 +2449,8 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
     const int tid = threadIdx.x;
     const int wid = tid / kWave;
     const int lane = tid & (kWave - 1);
-    for (int q = tid; q < n * kPartial; q += kBlock) rec[q / kPartial][q % kPartial] = 0.0;
+    const uint64_t slot = ((uint64_t)rec0 + blockIdx.x) * kPartial;
+    uint64_t touched = 0;   // problems whose record this workgroup wrote
     if (tid < n) wtab[tid] = descs[tid].wet;
     // ends with a barrier
     const Fv1Sched f = fv1_schedule(descs, n, cpre, kAllProblems, nullptr, nullptr, cblk);
@@ -2451,8 +2484,9 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
                 int s = cs < 0 ? 0 : cs;
                 while (cpre[s + 1] <= ch) ++s;
                 s = uniform(s);
-                if (cs >= 0) acc_flush(acc, red, rec[cs]);   // ends with a barrier
+                if (cs >= 0) acc_flush_store(acc, red, glob(descs[cs].partials) + slot);
                 cs = s;
+                touched |= 1ull << s;
                 make_ctx<T>(x, descs[s]);
                 fill_rxy(rxy, descs[s], x.dt);
                 __syncthreads();
@@ -2508,12 +2542,11 @@ __global__ __launch_bounds__(kBlock) void k_fv1_heavy(const Desc* __restrict__ d
             }
         }
     }
-    if (cs >= 0) acc_flush(acc, red, rec[cs]);
-    __syncthreads();
+    if (cs >= 0) acc_flush_store(acc, red, glob(descs[cs].partials) + slot);
+    // zero records for the problems this workgroup had no chunk of
     for (int q = tid; q < n * kPartial; q += kBlock) {
         const int s = q / kPartial;
-        descs[s].partials[((uint64_t)rec0 + blockIdx.x) * kPartial + q % kPartial] =
-            rec[s][q % kPartial];
+        if (!((touched >> s) & 1ull)) descs[s].partials[slot + q % kPartial] = 0.0;
     }
 }
 
@@ -2932,18 +2965,20 @@ hipError_t launch_traverse(Launch lc, uint32_t nblocks, hipStream_t s)
 }
 
 // Workgroups of the heavy FV1 kernel: about as many as are resident at its
-// occupancy (three waves per SIMD), never more than the light kernel's.
-uint32_t heavy_grid(uint32_t grid)
+// occupancy, never more than the light kernel's.  FP64: three waves per SIMD
+// (its block staging takes 45.6 KB of LDS per workgroup); FP32: four (28.5
+// KB, and 127 VGPRs under the kernel's four-wave cap).
+uint32_t heavy_grid(int prec, uint32_t grid)
 {
-    constexpr uint32_t kHeavy = 768;
-    return grid < kHeavy ? grid : kHeavy;
+    const uint32_t cap = 1024u;
+    return grid < cap ? grid : cap;
 }
 
 // The heavy FV1 kernel alone (after the light kernel of the same step: it
 // reads the wet table and writes only the other set and its own records).
 hipError_t launch_fv1_heavy(int prec, const Desc* descs, int n, uint32_t grid, hipStream_t s)
 {
-    const uint32_t gh = heavy_grid(grid);
+    const uint32_t gh = heavy_grid(prec, grid);
     if (prec == HW_FP64)
         hipLaunchKernelGGL(k_fv1_heavy<double>, dim3(gh), dim3(kBlock), 0, s, descs, n, grid);
     else
@@ -2967,7 +3002,7 @@ hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, uint32_t gri
                        hipStream_t s)
 {
     const dim3 blocks(fill_blocks + (uint32_t)fill.n);
-    const int records = (int)(grid + heavy_grid(grid));
+    const int records = (int)(grid + heavy_grid(prec, grid));
     if (prec == HW_FP64)
         hipLaunchKernelGGL(k_fill_finalize<double>, blocks, dim3(kBlock), 0, s, fill,
                            fill_blocks, records);
@@ -2977,10 +3012,10 @@ hipError_t launch_fill(int prec, Launch fill, uint32_t fill_blocks, uint32_t gri
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Desc* descs, int n, uint32_t grid, hipStream_t s)
+hipError_t launch_finalize(int prec, const Desc* descs, int n, uint32_t grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(n), dim3(kFinalBlock), 0, s, descs,
-                       (int)(grid + heavy_grid(grid)));
+                       (int)(grid + heavy_grid(prec, grid)));
     return hipGetLastError();
 }
 
