@@ -2430,9 +2430,11 @@ __global__ __launch_bounds__(kBlock) void k_fv1_light(const Desc* __restrict__ d
 // no wet super-chunk costs one round trip.  Every wave of a workgroup reads
 // the same words and so visits the same super-chunks, in ascending order.
 // Records go to slots [rec0, rec0 + gridDim.x).
-// Held to four waves per SIMD.
+// FP32 is held to four waves per SIMD (128 VGPRs, none spilled); FP64 stays
+// at three (158 VGPRs: held to four it spills 16 to scratch, whose traffic
+// takes back most of what the fourth wave gains).
 template <typename T>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
 void k_fv1_heavy(const Desc* __restrict__ descs, int n, uint32_t rec0)
 {
     constexpr uint32_t SC = kLeafBatch * kBlock;
@@ -2965,12 +2967,11 @@ hipError_t launch_traverse(Launch lc, uint32_t nblocks, hipStream_t s)
 }
 
 // Workgroups of the heavy FV1 kernel: about as many as are resident at its
-// occupancy, never more than the light kernel's.  FP64: three waves per SIMD
-// (its block staging takes 45.6 KB of LDS per workgroup); FP32: four (28.5
-// KB, and 127 VGPRs under the kernel's four-wave cap).
+// occupancy, never more than the light kernel's: four waves per SIMD for
+// FP32, three for FP64.
 uint32_t heavy_grid(int prec, uint32_t grid)
 {
-    const uint32_t cap = 1024u;
+    const uint32_t cap = prec == HW_FP64 ? 768u : 1024u;
     return grid < cap ? grid : cap;
 }
 
